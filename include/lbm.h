@@ -1,0 +1,210 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) implementation of the unified
+ * fourth-order BGK lattice Boltzmann model for the d-dimensional linear
+ * hyperbolic equation  d_t phi + u . grad phi = R  (Chen, Chai & Shi,
+ * arXiv:2410.13165).
+ *
+ * What one handle computes (paper references are to that article):
+ *   - the DdQ(2d^2+1) lattice of Sec. 2.3 (eqs. d1q3, d2q9, d3q19, ddqq), d = 1..4,
+ *     in lattice units c = 1, so dt = dx (acoustic scaling, Sec. 2.2 and Sec. 5);
+ *   - equilibria f^eq_k = omega_k phi and sources R_k = omega_k R with
+ *     omega = M^{-1} eps, eps from eq. (meq) and the fourth-order moment m4 from
+ *     eq. (meq-4rd) (Remark 5), g = 1/2 unless overridden;
+ *   - the BGK update eq. (BGK-LB-Evolution) with s = 1/tau (the paper's method is
+ *     s = 2, eq. BGK-LB-Evolution-seq2), fused with pull streaming;
+ *   - initialisation eq. (ini) / (ini-simp) of order K = 1 or 3;
+ *   - Dirichlet walls by the full-way schemes eq. (bun1) (orders 1, 3, 4) or the
+ *     half-way schemes eq. (bun2) (orders 1..4), the latter applied as
+ *     f_k(x_f, t+dt) = -f*_kbar(x_f, t) + [right side of bun2 at (x_b, t)],
+ *     with f* the post-collision value of eq. (collision) (Appendix A);
+ *   - diagnostics: phi, the RMSE of eq. (rmse) against an analytic solution, and
+ *     the total microscopic entropy sum_x sum_k f_k^2/(2 omega_k) (eqs. entropy,
+ *     skfk; conserved for s = 2, R = 0 on periodic lattices, Remark 6).
+ *
+ * Conventions for every call:
+ *   - Return value: LBM_OK (0) or a negative lbm_status.  Nothing throws across
+ *     the ABI.  The message of the last failure of a handle is returned by
+ *     lbm_last_error(handle); failures of lbm_create are reported by
+ *     lbm_last_error(NULL) (per thread).
+ *   - Node layout in device memory: x_1 fastest, then x_2, ..., x_d (C order of
+ *     an array shaped [N_d]...[N_1]).  dims[0] = N_1.
+ *   - Device buffers are owned by the handle and obtained through the allocator
+ *     callbacks of lbm_params (or hipMalloc when they are NULL).  Pointers passed
+ *     by the caller are borrowed for the duration of the call only.
+ *   - All device work is enqueued on lbm_params.stream (a hipStream_t borrowed
+ *     from the caller, never destroyed; NULL = the null stream).  Only
+ *     lbm_create with an analytic field, lbm_set_initial in LBM_FP32 mode and
+ *     lbm_moments with scalars_host != NULL synchronise that stream.
+ *   - A handle must not be used from two threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_MAX_DIM 4
+#define LBM_MAX_Q 33
+#define LBM_MAX_MODES 16
+#define LBM_NSCALARS 8
+
+typedef struct lbm_handle lbm_handle;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,        /* an argument is out of range or inconsistent     */
+  LBM_ENOMEM = -2,        /* a device allocation failed                      */
+  LBM_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed      */
+  LBM_EUNSUPPORTED = -4,  /* valid request this build does not provide       */
+  LBM_ENONFINITE = -5     /* reserved: non-finite values detected            */
+} lbm_status;
+
+/* Boundary condition of one axis (both faces of the axis take the same kind). */
+typedef enum {
+  LBM_BC_PERIODIC = 0,    /* periodic wrap, nodes at origin + i dx                       */
+  LBM_BC_FULLWAY = 1,     /* wall on the nodes i = 0 and i = N-1 (Fig. 1, full-way case)  */
+  LBM_BC_HALFWAY = 2      /* walls half a cell outside, nodes at origin + (i + 1/2) dx   */
+} lbm_bc;
+
+/* How populations are stored and updated. */
+typedef enum {
+  LBM_FP64 = 0,           /* post-collision populations in float64, float64 arithmetic   */
+  LBM_FP32 = 1,           /* post-collision populations in float32 as deviations from the
+                             uniform exact state omega_k (phi_mean + R t), float32
+                             arithmetic with compensated sums                            */
+  LBM_FP32_SPLIT = 2      /* phi in float64 plus g_k = f_k - omega_k phi in float32,
+                             float64 arithmetic                                          */
+} lbm_precision;
+
+/* Analytic solution family phi*(x, t) = F(x - u t) + R t used for the analytic
+   initial state, the Dirichlet data (with all its time and space derivatives,
+   which the wall schemes need) and the RMSE reference. */
+typedef enum {
+  LBM_FIELD_NONE = 0,
+  LBM_FIELD_COS_SUM = 1,     /* F(y) = sum_j a_j cos(kappa_j . y + theta_j)            */
+  LBM_FIELD_EXP_SUM = 2,     /* F(y) = sum_j a_j exp(kappa_j . y)                      */
+  LBM_FIELD_TANH_BUBBLE = 3  /* F(y) = 1/2 - 1/2 tanh((Rr - |y - center|)/(2W)),
+                                Example 2; periodic lattices only                        */
+} lbm_field_kind;
+
+typedef struct {
+  int32_t kind;                 /* lbm_field_kind                                   */
+  int32_t n_modes;              /* 1..LBM_MAX_MODES for the sums, ignored otherwise  */
+  const double* amps;           /* host, n_modes values a_j (copied)                 */
+  const double* kvecs;          /* host, n_modes x d row-major kappa_j (copied)      */
+  const double* phases;         /* host, n_modes values theta_j, or NULL for zeros   */
+  double Rr, W;                 /* tanh bubble radius and interface width            */
+  double center[LBM_MAX_DIM];   /* tanh bubble centre at t = 0                       */
+} lbm_field;
+
+typedef struct {
+  uint32_t struct_size;         /* sizeof(lbm_params), set by lbm_params_default     */
+  double dx;                    /* lattice spacing; dt = dx                           */
+  double origin[LBM_MAX_DIM];   /* a_l: lower end of the domain along each axis      */
+  double u[LBM_MAX_DIM];        /* transport velocity (sigma = u since c = 1)        */
+  double R;                     /* constant source term                               */
+  double g;                     /* interpolation weight of eq. (meq-4rd), default 1/2 */
+  double m4;                    /* explicit fourth-order moment when use_m4 != 0      */
+  int32_t use_m4;
+  int32_t bc[LBM_MAX_DIM];      /* lbm_bc per axis; full-way and half-way axes may
+                                   not be mixed in one lattice                        */
+  int32_t bc_order;             /* P: full-way {1,3,4}, half-way {1,2,3,4}; default 4 */
+  int32_t init_order;           /* K in {1,3}; default 3                              */
+  int32_t precision;            /* lbm_precision; default LBM_FP64                    */
+  const lbm_field* field;       /* NULL: the caller must call lbm_set_initial, and
+                                   every axis must be periodic                        */
+  void* (*alloc)(size_t bytes, void* ctx);   /* device allocator, NULL = hipMalloc  */
+  void (*free_fn)(void* ptr, void* ctx);     /* matching free, NULL = hipFree       */
+  void* alloc_ctx;
+  void* stream;                 /* hipStream_t used for all work, borrowed            */
+} lbm_params;
+
+typedef struct {
+  int32_t d, q;
+  int32_t precision;
+  int32_t entropy_stable;       /* 1 when every omega_k > 0 (Sec. 4.1)               */
+  int64_t dims[LBM_MAX_DIM];
+  int64_t nodes;                /* prod(dims)                                         */
+  int64_t step;                 /* n: the state holds time t_n = n dt                 */
+  double omega[LBM_MAX_Q];      /* EDF weights in the velocity order of Sec. 2.3      */
+  double m4, min_omega;
+  double s, dt;
+  double phi_ref;               /* LBM_FP32: phi_mean of the deviation reference      */
+  int32_t bytes_per_lu;         /* algorithmic HBM bytes per lattice update of a step */
+  int32_t reserved;
+} lbm_info_t;
+
+/* Fill p with defaults: dx = 1, origin 0, u 0, R 0, g = 1/2, all axes periodic,
+   P = 4, K = 3, LBM_FP64, no field, hipMalloc/hipFree, null stream. */
+void lbm_params_default(lbm_params* p);
+
+/* Create a lattice with d in 1..4 axes of dims[0..d-1] nodes and relaxation time
+   tau = 1/s > 0 (the paper's method: tau = 1/2).  Computes eps, m4 and omega
+   (Sec. 2.3, eqs. meq, meq-4rd, omega_k-2), allocates two state buffers and,
+   when p->field is given, writes the initial state of order p->init_order
+   (eq. ini-simp) from the analytic field.  Parameters outside the entropy-stability
+   region are accepted; lbm_info reports min_omega and entropy_stable.
+   Errors: LBM_EINVAL (d, dims, tau, dx, orders, bc codes, a Dirichlet axis without
+   a field, fewer than 2 nodes on a Dirichlet axis, more than 2^31-1 nodes),
+   LBM_EUNSUPPORTED (mixed full-way/half-way axes, a tanh field with walls),
+   LBM_ENOMEM, LBM_EDEVICE.  On failure *out is NULL. */
+int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p,
+               lbm_handle** out);
+
+/* Initial state at t = 0 from a device float64 field phi0 (layout above) and,
+   for K = 3, its gradient grad_phi0 (device float64, d planes of N nodes, plane j
+   holding d phi0 / d x_{j+1}).  grad_phi0 = NULL uses fourth-order central
+   differences, which needs every axis periodic (LBM_EINVAL otherwise).  Resets
+   the step counter to 0. */
+int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_phi0_dev);
+
+/* Advance n >= 0 time steps: n launches of the fused pull-stream + collide
+   kernel with the wall schemes applied inline.  Asynchronous on the stream. */
+int lbm_step(lbm_handle* h, int64_t n);
+
+/* Moments of the current state t_n.
+   phi_out_dev (nullable): device float64 buffer of N nodes that receives
+     phi(x, t_n) = sum_k f_k (pre-collision, eq. 0-1-meq).
+   scalars_host (nullable): host buffer of LBM_NSCALARS doubles that receives
+     [0] sum_x phi, [1] sum_x phi^2, [2] sum_x (phi - phi*)^2 (NaN without a field),
+     [3] sum_x sum_k f_k^2 / (2 omega_k) over the pre-collision populations
+         (NaN when s = 1, where they cannot be recovered from the stored state),
+     [4] max_x |phi|, [5] number of non-finite phi values,
+     [6] RMSE of eq. (rmse) = sqrt([2] / N), [7] t_n.
+   The reductions are float64 and deterministic; this call synchronises the
+   stream when scalars_host is given. */
+int lbm_moments(lbm_handle* h, double* phi_out_dev, double* scalars_host);
+
+int lbm_info(const lbm_handle* h, lbm_info_t* out);
+
+/* Size in bytes of the state blob used by lbm_get_state / lbm_set_state. */
+int64_t lbm_state_bytes(const lbm_handle* h);
+/* Device-to-device copy of the current state (for checkpoints). */
+int lbm_get_state(const lbm_handle* h, void* dst_dev);
+/* Replace the state by a blob from lbm_get_state of a handle with the same
+   parameters, taken at step `step`. */
+int lbm_set_state(lbm_handle* h, const void* src_dev, int64_t step);
+
+/* Host-only helper (no device work): the EDF weights of a DdQ(2d^2+1) lattice.
+   omega_out receives 2d^2+1 values in the velocity order of Sec. 2.3, from the
+   closed form eq. (omega_k-2) with one m4 for every pair (Remark 5); m4 is the
+   interpolation eq. (meq-4rd) with weight g (NaN = 1/2) unless use_m4 != 0.
+   m4_out and min_omega_out are nullable.  Entropy stability (Sec. 4.1) holds
+   iff *min_omega_out > 0.  Returns LBM_EINVAL for d outside 1..4 or null
+   u / omega_out. */
+int lbm_equilibrium_weights(int d, const double* u, double g, int use_m4, double m4,
+                            double* omega_out, double* m4_out, double* min_omega_out);
+
+const char* lbm_last_error(const lbm_handle* h);
+
+/* Release all device memory of h (through free_fn).  NULL is accepted. */
+int lbm_destroy(lbm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

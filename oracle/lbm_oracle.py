@@ -296,7 +296,8 @@ class Problem:
     "periodic" (both faces), "fullway", "halfway" or "open".  An "open" face
     just wraps around and is only meant for sub-boxes whose edge values are
     discarded.  Node positions: x = a + i dx on periodic/full-way axes,
-    x = a + (i + 1/2) dx on axes with a half-way face (eq. rmse, Fig. 1).
+    x = a + (i + 1/2) dx on axes with a half-way face (eq. rmse, Fig. 1);
+    `shift` overrides that offset (sub-boxes of a half-way lattice).
     """
     d: int
     dims: Sequence[int]
@@ -311,6 +312,7 @@ class Problem:
     g: float = 0.5
     m4: Optional[float] = None
     field: Optional[ExactField] = None
+    shift: Optional[Sequence[float]] = None  # node offset per axis, in units of dx
 
     def __post_init__(self):
         self.dims = tuple(int(n) for n in self.dims)
@@ -331,7 +333,10 @@ class Problem:
 
     def axis_coords(self, j: int) -> np.ndarray:
         n = np.arange(self.dims[j], dtype=np.float64)
-        shift = 0.5 if HALFWAY in self.bc[j] else 0.0
+        if self.shift is not None:
+            shift = float(self.shift[j])
+        else:
+            shift = 0.5 if HALFWAY in self.bc[j] else 0.0
         return self.origin[j] + (n + shift) * self.dx
 
     def nodes(self) -> np.ndarray:

@@ -1,0 +1,491 @@
+// C ABI of the lattice Boltzmann library (declarations and contracts in
+// include/lbm.h): argument checking, the host-side parameter maths
+// (eps, m4, omega of Sec. 2.3 and Remark 5), buffer management and the
+// stream-ordered launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "engine.hpp"
+
+using namespace lbm;
+
+struct lbm_handle {
+  KParams kp{};
+  int d = 0, q = 0;
+  int64_t dims[kMaxDim] = {1, 1, 1, 1};
+  int64_t nodes = 0;
+  int precision = LBM_FP64;
+  double m4 = 0.0, min_omega = 0.0;
+  int entropy_stable = 0;
+  hipStream_t stream = nullptr;
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_ctx = nullptr;
+  void* buf[2] = {nullptr, nullptr};     // populations (or g in split mode)
+  double* phib[2] = {nullptr, nullptr};  // split mode: phi
+  double* partial = nullptr;             // kRedBlocks x kNumAcc
+  double* result = nullptr;              // kNumAcc
+  int cur = 0;
+  int64_t step = 0;
+  bool initialised = false;
+  std::string err;
+};
+
+static thread_local std::string g_create_error;
+
+namespace {
+
+int fail(lbm_handle* h, int code, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_create_error = msg;
+  return code;
+}
+
+int hip_fail(lbm_handle* h, hipError_t e, const char* what) {
+  return fail(h, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* dev_alloc(lbm_handle* h, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (h->alloc) return h->alloc(bytes, h->alloc_ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(lbm_handle* h, void* p) {
+  if (!p) return;
+  if (h->free_fn)
+    h->free_fn(p, h->alloc_ctx);
+  else
+    (void)hipFree(p);
+}
+
+size_t elem_size(int precision) { return precision == LBM_FP64 ? 8 : 4; }
+
+size_t pop_bytes(const lbm_handle* h) {
+  return static_cast<size_t>(h->kp.pstride) * h->q * elem_size(h->precision);
+}
+
+size_t phi_bytes(const lbm_handle* h) { return static_cast<size_t>(h->nodes) * sizeof(double); }
+
+void release(lbm_handle* h) {
+  for (int i = 0; i < 2; ++i) {
+    dev_free(h, h->buf[i]);
+    dev_free(h, h->phib[i]);
+    h->buf[i] = nullptr;
+    h->phib[i] = nullptr;
+  }
+  dev_free(h, h->partial);
+  dev_free(h, h->result);
+  h->partial = h->result = nullptr;
+}
+
+// Copy the analytic field into the kernel parameter block.
+int setup_field(lbm_handle* h, const lbm_field* fld) {
+  FieldDev& F = h->kp.field;
+  std::memset(&F, 0, sizeof(F));
+  F.kind = kFieldNone;
+  if (!fld || fld->kind == LBM_FIELD_NONE) return LBM_OK;
+  const int d = h->d;
+  if (fld->kind == LBM_FIELD_TANH_BUBBLE) {
+    if (!(fld->W > 0.0)) return fail(nullptr, LBM_EINVAL, "tanh field needs W > 0");
+    F.kind = kFieldTanh;
+    F.Rr = fld->Rr;
+    F.W = fld->W;
+    for (int a = 0; a < d; ++a) F.center[a] = fld->center[a];
+    return LBM_OK;
+  }
+  if (fld->kind != LBM_FIELD_COS_SUM && fld->kind != LBM_FIELD_EXP_SUM)
+    return fail(nullptr, LBM_EINVAL, "unknown field kind");
+  if (fld->n_modes < 1 || fld->n_modes > kMaxModes)
+    return fail(nullptr, LBM_EINVAL, "field n_modes must be in 1..16");
+  if (!fld->amps || !fld->kvecs) return fail(nullptr, LBM_EINVAL, "field amps/kvecs missing");
+  F.kind = fld->kind == LBM_FIELD_COS_SUM ? kFieldCos : kFieldExp;
+  F.nmodes = fld->n_modes;
+  for (int j = 0; j < F.nmodes; ++j) {
+    F.amp[j] = fld->amps[j];
+    F.phase[j] = fld->phases ? fld->phases[j] : 0.0;
+    double ku = 0.0;
+    for (int a = 0; a < d; ++a) {
+      const double k = fld->kvecs[j * d + a];
+      if (!std::isfinite(k)) return fail(nullptr, LBM_EINVAL, "non-finite wave vector");
+      F.kvec[j][a] = k;
+      ku += k * h->kp.u[a];
+    }
+    F.ku[j] = ku;
+  }
+  return LBM_OK;
+}
+
+void setup_faces(KParams& kp, int d) {
+  kp.nfaces = 0;
+  kp.wall_nodes = 0;
+  for (int a = 0; a < d; ++a) {
+    if (kp.bc[a] == LBM_BC_PERIODIC) continue;
+    long long cnt = 1;
+    for (int b = 0; b < d; ++b) {
+      if (b == a) continue;
+      const bool inner = (b < a) && kp.bc[b] != LBM_BC_PERIODIC;
+      cnt *= inner ? (kp.n[b] - 2) : kp.n[b];
+    }
+    for (int side = 0; side < 2; ++side) {
+      kp.face_axis[kp.nfaces] = a;
+      kp.face_side[kp.nfaces] = side;
+      kp.face_count[kp.nfaces] = cnt;
+      kp.wall_nodes += cnt;
+      ++kp.nfaces;
+    }
+  }
+}
+
+int sync_result(lbm_handle* h, double* host) {
+  hipError_t e = hipMemcpyAsync(host, h->result, kNumAcc * sizeof(double), hipMemcpyDeviceToHost,
+                                h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+// FP32 mode: the deviations are taken from omega_k (mean(phi0) + R t).
+int compute_reference(lbm_handle* h, const double* phi0) {
+  if (h->precision != LBM_FP32) {
+    h->kp.phi_ref = 0.0;
+    return LBM_OK;
+  }
+  hipError_t e = launch_sum_phi0(h->kp, phi0, h->partial, h->result, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sum of phi0");
+  double host[kNumAcc];
+  int rc = sync_result(h, host);
+  if (rc != LBM_OK) return rc;
+  h->kp.phi_ref = host[0] / static_cast<double>(h->nodes);
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_params_default(lbm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(lbm_params);
+  p->dx = 1.0;
+  p->g = 0.5;
+  p->bc_order = 4;
+  p->init_order = 3;
+  p->precision = LBM_FP64;
+}
+
+int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_handle** out) {
+  if (out) *out = nullptr;
+  if (!out || !dims || !p) return fail(nullptr, LBM_EINVAL, "null argument");
+  if (p->struct_size != sizeof(lbm_params))
+    return fail(nullptr, LBM_EINVAL, "lbm_params.struct_size mismatch (use lbm_params_default)");
+  if (d < 1 || d > kMaxDim) return fail(nullptr, LBM_EINVAL, "d must be in 1..4");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(nullptr, LBM_EINVAL, "tau must be > 0");
+  if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(nullptr, LBM_EINVAL, "dx must be > 0");
+  if (p->precision < LBM_FP64 || p->precision > LBM_FP32_SPLIT)
+    return fail(nullptr, LBM_EINVAL, "unknown precision");
+  if (p->init_order != 1 && p->init_order != 3)
+    return fail(nullptr, LBM_EINVAL, "init_order must be 1 or 3");
+  int64_t nodes = 1;
+  int scheme = kNoWall;
+  for (int a = 0; a < d; ++a) {
+    if (dims[a] < 1) return fail(nullptr, LBM_EINVAL, "dims must be >= 1");
+    if (dims[a] > (int64_t(1) << 30)) return fail(nullptr, LBM_EINVAL, "dimension too large");
+    nodes *= dims[a];
+    if (nodes > std::numeric_limits<int32_t>::max())
+      return fail(nullptr, LBM_EINVAL, "more than 2^31-1 nodes");
+    const int bc = p->bc[a];
+    if (bc != LBM_BC_PERIODIC && bc != LBM_BC_FULLWAY && bc != LBM_BC_HALFWAY)
+      return fail(nullptr, LBM_EINVAL, "unknown boundary code");
+    if (bc != LBM_BC_PERIODIC) {
+      if (dims[a] < 2) return fail(nullptr, LBM_EINVAL, "a Dirichlet axis needs >= 2 nodes");
+      const int sch = bc == LBM_BC_FULLWAY ? kFullWay : kHalfWay;
+      if (scheme != kNoWall && scheme != sch)
+        return fail(nullptr, LBM_EUNSUPPORTED, "full-way and half-way axes cannot be mixed");
+      scheme = sch;
+    }
+  }
+  if (scheme == kFullWay && p->bc_order != 1 && p->bc_order != 3 && p->bc_order != 4)
+    return fail(nullptr, LBM_EINVAL, "full-way order must be 1, 3 or 4");
+  if (scheme == kHalfWay && (p->bc_order < 1 || p->bc_order > 4))
+    return fail(nullptr, LBM_EINVAL, "half-way order must be 1..4");
+  if (scheme != kNoWall && (!p->field || p->field->kind == LBM_FIELD_NONE))
+    return fail(nullptr, LBM_EINVAL, "Dirichlet walls need an analytic field for their data");
+  if (scheme != kNoWall && p->field->kind == LBM_FIELD_TANH_BUBBLE)
+    return fail(nullptr, LBM_EUNSUPPORTED, "the tanh field supplies no wall derivatives");
+
+  lbm_handle* h = new (std::nothrow) lbm_handle();
+  if (!h) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+  h->d = d;
+  h->q = q_of(d);
+  h->nodes = nodes;
+  h->precision = p->precision;
+  h->stream = static_cast<hipStream_t>(p->stream);
+  h->alloc = p->alloc;
+  h->free_fn = p->free_fn;
+  h->alloc_ctx = p->alloc_ctx;
+  if ((h->alloc == nullptr) != (h->free_fn == nullptr)) {
+    delete h;
+    return fail(nullptr, LBM_EINVAL, "alloc and free_fn must both be set or both be NULL");
+  }
+
+  KParams& kp = h->kp;
+  kp.d = d;
+  kp.q = h->q;
+  int64_t st = 1;
+  for (int a = 0; a < kMaxDim; ++a) {
+    const int64_t n = a < d ? dims[a] : 1;
+    h->dims[a] = n;
+    kp.n[a] = static_cast<int>(n);
+    kp.stride[a] = static_cast<int>(st);
+    st *= n;
+    kp.bc[a] = a < d ? p->bc[a] : 0;
+    kp.origin[a] = a < d ? p->origin[a] : 0.0;
+    kp.u[a] = a < d ? p->u[a] : 0.0;
+    kp.shift[a] = (a < d && p->bc[a] == LBM_BC_HALFWAY) ? 0.5 : 0.0;
+  }
+  kp.nodes = static_cast<int>(nodes);
+  kp.rows = static_cast<int>(nodes / dims[0]);
+  kp.pstride = (nodes + 63) / 64 * 64;  // 256-byte aligned population planes
+  kp.scheme = scheme;
+  kp.P = p->bc_order;
+  kp.K = p->init_order;
+  kp.tau = tau;
+  kp.s = 1.0 / tau;
+  kp.s_f = static_cast<float>(kp.s);
+  kp.dx = p->dx;
+  kp.dt = p->dx;  // c = 1
+  kp.R = p->R;
+  setup_faces(kp, d);
+
+  // eps and omega: eq. (meq), eq. (meq-4rd) with g, closed form eq. (omega_k-2)
+  double u[kMaxDim] = {0, 0, 0, 0};
+  for (int a = 0; a < d; ++a) {
+    u[a] = p->u[a];
+    if (!std::isfinite(u[a])) {
+      delete h;
+      return fail(nullptr, LBM_EINVAL, "non-finite u");
+    }
+  }
+  double g = std::isnan(p->g) ? 0.5 : p->g;
+  h->m4 = (d >= 2) ? (p->use_m4 ? p->m4 : m4_interpolated(d, u, g)) : 0.0;
+  omega_closed_form(d, u, h->m4, kp.omega);
+  h->min_omega = kp.omega[0];
+  for (int k = 0; k < h->q; ++k) {
+    kp.omega_f[k] = static_cast<float>(kp.omega[k]);
+    h->min_omega = std::fmin(h->min_omega, kp.omega[k]);
+  }
+  h->entropy_stable = h->min_omega > 0.0 ? 1 : 0;
+  for (int k = 0; k < h->q; ++k) {
+    for (int a = 0; a < kMaxDim; ++a)
+      kp.cv[k][a] = static_cast<signed char>(a < d ? vel_comp(d, k, a) : 0);
+    kp.kbar[k] = opp_index(d, k);
+  }
+
+  if (int rc = setup_field(h, p->field); rc != LBM_OK) {
+    delete h;
+    return rc;
+  }
+
+  // device buffers
+  const size_t pb = pop_bytes(h);
+  for (int i = 0; i < 2; ++i) {
+    h->buf[i] = dev_alloc(h, pb);
+    if (h->precision == LBM_FP32_SPLIT) h->phib[i] = static_cast<double*>(dev_alloc(h, phi_bytes(h)));
+  }
+  h->partial = static_cast<double*>(dev_alloc(h, sizeof(double) * kRedBlocks * kNumAcc));
+  h->result = static_cast<double*>(dev_alloc(h, sizeof(double) * kNumAcc));
+  bool ok = h->buf[0] && h->buf[1] && h->partial && h->result;
+  if (h->precision == LBM_FP32_SPLIT) ok = ok && h->phib[0] && h->phib[1];
+  if (!ok) {
+    release(h);
+    delete h;
+    return fail(nullptr, LBM_ENOMEM, "device allocation failed");
+  }
+  // Deterministic content for the padding between population planes.
+  for (int i = 0; i < 2; ++i) {
+    hipError_t e = hipMemsetAsync(h->buf[i], 0, pb, h->stream);
+    if (e != hipSuccess) {
+      int rc = hip_fail(nullptr, e, "hipMemsetAsync");
+      release(h);
+      delete h;
+      return rc;
+    }
+  }
+
+  if (kp.field.kind != kFieldNone) {
+    int rc = compute_reference(h, nullptr);
+    if (rc == LBM_OK) {
+      hipError_t e = launch_init(kp, h->precision, h->buf[0], h->phib[0], nullptr, nullptr,
+                                 h->stream);
+      if (e != hipSuccess) rc = hip_fail(h, e, "initialisation kernel");
+    }
+    if (rc == LBM_OK) {
+      hipError_t e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) rc = hip_fail(h, e, "hipStreamSynchronize");
+    }
+    if (rc != LBM_OK) {
+      g_create_error = h->err;
+      release(h);
+      delete h;
+      return rc;
+    }
+    h->initialised = true;
+  }
+  h->cur = 0;
+  h->step = 0;
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_phi0_dev) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+  if (!phi0_dev) return fail(h, LBM_EINVAL, "phi0 is NULL");
+  if (h->kp.K == 3 && !grad_phi0_dev) {
+    for (int a = 0; a < h->d; ++a)
+      if (h->kp.bc[a] != LBM_BC_PERIODIC)
+        return fail(h, LBM_EINVAL, "finite-difference gradients need periodic axes");
+  }
+  int rc = compute_reference(h, phi0_dev);
+  if (rc != LBM_OK) return rc;
+  hipError_t e = launch_init(h->kp, h->precision, h->buf[0], h->phib[0], phi0_dev, grad_phi0_dev,
+                             h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "initialisation kernel");
+  h->cur = 0;
+  h->step = 0;
+  h->initialised = true;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int64_t n) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+  if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
+  if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state (call lbm_set_initial)");
+  for (int64_t i = 0; i < n; ++i) {
+    const int src = h->cur, dst = 1 - h->cur;
+    hipError_t e = launch_step(h->kp, h->precision, h->buf[src], h->buf[dst], h->phib[src],
+                               h->phib[dst], h->step, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "step kernel");
+    h->cur = dst;
+    ++h->step;
+  }
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_handle* h, double* phi_out_dev, double* scalars_host) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+  if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state");
+  if (!phi_out_dev && !scalars_host) return LBM_OK;
+  hipError_t e = launch_moments(h->kp, h->precision, h->buf[h->cur], h->phib[h->cur], h->step,
+                                phi_out_dev, h->partial, h->result, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "moments kernel");
+  if (!scalars_host) return LBM_OK;
+  double acc[kNumAcc];
+  int rc = sync_result(h, acc);
+  if (rc != LBM_OK) return rc;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  const bool has_field = h->kp.field.kind != kFieldNone;
+  scalars_host[0] = acc[0];
+  scalars_host[1] = acc[1];
+  scalars_host[2] = has_field ? acc[2] : nan;
+  scalars_host[3] = (h->precision != LBM_FP32_SPLIT && h->kp.s == 1.0) ? nan : acc[3];
+  scalars_host[4] = acc[4];
+  scalars_host[5] = acc[5];
+  scalars_host[6] = has_field ? std::sqrt(acc[2] / static_cast<double>(h->nodes)) : nan;
+  scalars_host[7] = static_cast<double>(h->step) * h->kp.dt;
+  return LBM_OK;
+}
+
+int lbm_info(const lbm_handle* h, lbm_info_t* out) {
+  if (!h || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  out->d = h->d;
+  out->q = h->q;
+  out->precision = h->precision;
+  out->entropy_stable = h->entropy_stable;
+  for (int a = 0; a < kMaxDim; ++a) out->dims[a] = a < h->d ? h->dims[a] : 0;
+  out->nodes = h->nodes;
+  out->step = h->step;
+  for (int k = 0; k < h->q; ++k) out->omega[k] = h->kp.omega[k];
+  out->m4 = h->m4;
+  out->min_omega = h->min_omega;
+  out->s = h->kp.s;
+  out->dt = h->kp.dt;
+  out->phi_ref = h->kp.phi_ref;
+  const int es = static_cast<int>(elem_size(h->precision));
+  out->bytes_per_lu = 2 * h->q * es + (h->precision == LBM_FP32_SPLIT ? 16 : 0);
+  return LBM_OK;
+}
+
+int64_t lbm_state_bytes(const lbm_handle* h) {
+  if (!h) return -1;
+  int64_t b = static_cast<int64_t>(pop_bytes(h));
+  if (h->precision == LBM_FP32_SPLIT) b += static_cast<int64_t>(phi_bytes(h));
+  return b;
+}
+
+int lbm_get_state(const lbm_handle* h, void* dst_dev) {
+  if (!h || !dst_dev) return fail(nullptr, LBM_EINVAL, "null argument");
+  lbm_handle* mh = const_cast<lbm_handle*>(h);
+  hipError_t e = hipMemcpyAsync(dst_dev, h->buf[h->cur], pop_bytes(h), hipMemcpyDeviceToDevice,
+                                h->stream);
+  if (e == hipSuccess && h->precision == LBM_FP32_SPLIT)
+    e = hipMemcpyAsync(static_cast<char*>(dst_dev) + pop_bytes(h), h->phib[h->cur], phi_bytes(h),
+                       hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(mh, e, "hipMemcpyAsync");
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_handle* h, const void* src_dev, int64_t step) {
+  if (!h || !src_dev) return fail(nullptr, LBM_EINVAL, "null argument");
+  if (step < 0) return fail(h, LBM_EINVAL, "step must be >= 0");
+  hipError_t e = hipMemcpyAsync(h->buf[h->cur], src_dev, pop_bytes(h), hipMemcpyDeviceToDevice,
+                                h->stream);
+  if (e == hipSuccess && h->precision == LBM_FP32_SPLIT)
+    e = hipMemcpyAsync(h->phib[h->cur], static_cast<const char*>(src_dev) + pop_bytes(h),
+                       phi_bytes(h), hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync");
+  h->step = step;
+  h->initialised = true;
+  return LBM_OK;
+}
+
+int lbm_equilibrium_weights(int d, const double* u, double g, int use_m4, double m4,
+                            double* omega_out, double* m4_out, double* min_omega_out) {
+  if (d < 1 || d > kMaxDim || !u || !omega_out)
+    return fail(nullptr, LBM_EINVAL, "d must be in 1..4 and u, omega_out non-NULL");
+  if (std::isnan(g)) g = 0.5;
+  const double mm = (d >= 2) ? (use_m4 ? m4 : m4_interpolated(d, u, g)) : 0.0;
+  omega_closed_form(d, u, mm, omega_out);
+  double mn = omega_out[0];
+  for (int k = 1; k < q_of(d); ++k) mn = std::fmin(mn, omega_out[k]);
+  if (m4_out) *m4_out = mm;
+  if (min_omega_out) *min_omega_out = mn;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_handle* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int lbm_destroy(lbm_handle* h) {
+  if (!h) return LBM_OK;
+  (void)hipStreamSynchronize(h->stream);
+  release(h);
+  delete h;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Device-side parameter block and kernel launchers shared by the C ABI layer
+// (capi.hip) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+constexpr int kMaxModes = 16;
+constexpr int kNumAcc = 6;        // accumulators of the moment reduction
+constexpr int kRedBlocks = 1024;  // fixed grid of the deterministic reductions
+constexpr int kRedThreads = 256;
+
+enum Scheme : int { kNoWall = 0, kFullWay = 1, kHalfWay = 2 };
+enum Mode : int { kFP64 = 0, kFP32 = 1, kSplit = 2 };
+enum FieldKind : int { kFieldNone = 0, kFieldCos = 1, kFieldExp = 2, kFieldTanh = 3 };
+
+// Analytic solution phi*(x, t) = F(x - u t) + R t (see include/lbm.h).
+struct FieldDev {
+  int kind;
+  int nmodes;
+  double amp[kMaxModes];
+  double phase[kMaxModes];
+  double ku[kMaxModes];                 // kappa_j . u
+  double kvec[kMaxModes][kMaxDim];
+  double Rr, W;
+  double center[kMaxDim];
+};
+
+// Everything a kernel needs about one lattice, passed by value.
+struct KParams {
+  int d, q;
+  int n[kMaxDim];          // nodes per axis, n[0] fastest in memory
+  int stride[kMaxDim];     // node strides
+  int nodes;
+  int rows;                // nodes / n[0]
+  long long pstride;       // elements between two population planes
+  int bc[kMaxDim];         // 0 periodic, 1 full-way, 2 half-way
+  int scheme;              // Scheme of the Dirichlet axes
+  int P;                   // wall scheme order
+  int K;                   // initialisation order
+  double omega[kMaxQ];
+  float omega_f[kMaxQ];
+  signed char cv[kMaxQ][kMaxDim];  // velocities (Sec. 2.3 order)
+  int kbar[kMaxQ];                 // c_kbar = -c_k
+  double s, tau, dt, dx, R;
+  float s_f;
+  double origin[kMaxDim];
+  double shift[kMaxDim];   // 1/2 on half-way axes, else 0
+  double u[kMaxDim];
+  double phi_ref;          // FP32 mode: mean of phi0
+  // wall nodes, listed face by face (see k_wall)
+  int nfaces;
+  int face_axis[2 * kMaxDim];
+  int face_side[2 * kMaxDim];
+  long long face_count[2 * kMaxDim];
+  long long wall_nodes;
+  FieldDev field;
+};
+
+struct LaunchShape {
+  int tx, ty;
+  unsigned blocks;
+};
+
+LaunchShape step_shape(const KParams& p);
+
+// One time step t_n -> t_{n+1}.  Non-split modes read/write post-collision
+// populations; split mode reads/writes (phi, g) pre-collision.
+hipError_t launch_step(const KParams& p, int mode, const void* src, void* dst,
+                       const double* phi_src, double* phi_dst, long long n,
+                       hipStream_t stream);
+
+// Initial state from the analytic field (phi0 == nullptr) or from device
+// arrays (grad0 == nullptr: fourth-order central differences).
+hipError_t launch_init(const KParams& p, int mode, void* dst, double* phi_dst,
+                       const double* phi0, const double* grad0, hipStream_t stream);
+
+// Moments of the state at step n; writes kRedBlocks x kNumAcc partials, then
+// the final kNumAcc values into out.
+hipError_t launch_moments(const KParams& p, int mode, const void* f, const double* phi,
+                          long long n, double* phi_out, double* partial, double* out,
+                          hipStream_t stream);
+
+// Sum over the nodes of phi0 (analytic when arr == nullptr), into out[0].
+hipError_t launch_sum_phi0(const KParams& p, const double* arr, double* partial,
+                           double* out, hipStream_t stream);
+
+}  // namespace lbm

@@ -1,0 +1,854 @@
+// gfx950 kernels of the fourth-order BGK lattice Boltzmann model.
+//
+// k_step       fused pull-streaming + BGK collision (eq. BGK-LB-Evolution) over
+//              the DdQ(2d^2+1) lattice, for every node not on a Dirichlet wall.
+// k_wall       the same update for the wall nodes, with the full-way (eq. bun1)
+//              or half-way (eq. bun2) formulas replacing the populations whose
+//              upwind node lies outside the domain.  Launched after k_step on
+//              the same stream; the two kernels write disjoint nodes.
+// k_step_split, k_wall_split
+//              the same step on the (phi float64, g = f - omega phi float32)
+//              representation.
+// k_init       initial state of order K = 1 or 3 (eq. ini-simp).
+// k_moments    phi, RMSE (eq. rmse), total microscopic entropy (eq. skfk) and
+//              safety statistics as deterministic float64 reductions.
+//
+// Memory layout: structure of arrays, population k of node `node` at
+// base[k * pstride + node], nodes ordered with x_1 fastest.  A block covers
+// ty rows of tx threads along x_1; a thread handles the nodes x, x + tx, ...
+// of its row.  The update reads every stored population once and writes every
+// population once per step, so the kernel is bound by HBM bandwidth; there is
+// no contraction to put on the matrix cores.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "engine.hpp"
+
+namespace lbm {
+
+// ----------------------------------------------------------------- helpers --
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+struct Vec4i {
+  int v[4];
+};
+
+constexpr Vec4i vel_vec(int D, int k) {
+  Vec4i r{{0, 0, 0, 0}};
+  for (int a = 0; a < D; ++a) r.v[a] = vel_comp(D, k, a);
+  return r;
+}
+
+template <int D>
+struct RowInfo {
+  int i[D];
+  int dm[D];     // node offset of the upwind neighbour for c_a = +1 (wrapped)
+  int dp[D];     // node offset of the upwind neighbour for c_a = -1 (wrapped)
+  bool lo[D];    // node lies on the lower Dirichlet wall of axis a
+  bool hi[D];    // node lies on the upper Dirichlet wall of axis a
+  bool rowwall;  // some axis a >= 1 puts the whole row on a wall
+  int rowbase;
+};
+
+template <int D>
+__device__ __forceinline__ void row_setup(const KParams& p, int row, RowInfo<D>& r) {
+  int rr = row;
+  r.rowwall = false;
+#pragma unroll
+  for (int a = 1; a < D; ++a) {
+    const int n = p.n[a];
+    const int ia = rr % n;
+    rr /= n;
+    const int st = p.stride[a];
+    r.i[a] = ia;
+    r.dm[a] = (ia == 0) ? (n - 1) * st : -st;
+    r.dp[a] = (ia == n - 1) ? -(n - 1) * st : st;
+    const bool wall = p.bc[a] != 0;
+    r.lo[a] = wall && ia == 0;
+    r.hi[a] = wall && ia == n - 1;
+    r.rowwall = r.rowwall || r.lo[a] || r.hi[a];
+  }
+  r.rowbase = row * p.n[0];
+}
+
+template <int D>
+__device__ __forceinline__ void col_setup(const KParams& p, int x, RowInfo<D>& r) {
+  const int n0 = p.n[0];
+  r.i[0] = x;
+  r.dm[0] = (x == 0) ? n0 - 1 : -1;
+  r.dp[0] = (x == n0 - 1) ? -(n0 - 1) : 1;
+  const bool wall = p.bc[0] != 0;
+  r.lo[0] = wall && x == 0;
+  r.hi[0] = wall && x == n0 - 1;
+}
+
+template <int D, int k>
+__device__ __forceinline__ int pull_offset(const RowInfo<D>& r) {
+  constexpr Vec4i c = vel_vec(D, k);
+  int off = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (c.v[a] == 1) off += r.dm[a];
+    if (c.v[a] == -1) off += r.dp[a];
+  }
+  return off;
+}
+
+template <int D, int k>
+__device__ __forceinline__ bool outside(const RowInfo<D>& r) {
+  constexpr Vec4i c = vel_vec(D, k);
+  bool o = false;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (c.v[a] == 1) o = o || r.lo[a];
+    if (c.v[a] == -1) o = o || r.hi[a];
+  }
+  return o;
+}
+
+template <int D>
+__device__ __forceinline__ bool on_wall(const RowInfo<D>& r) {
+  return r.rowwall || r.lo[0] || r.hi[0];
+}
+
+// Error-free sum a + b = s + e (Knuth's TwoSum), used for the compensated
+// float32 moment sums.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+// -------------------------------------------------- analytic field values ---
+
+// phi*(x, t) for the RMSE reference and the analytic initial state.
+template <int D>
+__device__ double field_value(const FieldDev& F, const KParams& p, const double (&x)[D],
+                              double t) {
+  double v = 0.0;
+  if (F.kind == kFieldTanh) {
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double y = x[a] - p.u[a] * t - F.center[a];
+      r2 += y * y;
+    }
+    v = 0.5 - 0.5 * tanh((F.Rr - sqrt(r2)) / (2.0 * F.W));
+  } else {
+    for (int j = 0; j < F.nmodes; ++j) {
+      double ph = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) ph += F.kvec[j][a] * (x[a] - p.u[a] * t);
+      v += (F.kind == kFieldCos) ? F.amp[j] * cos(ph + F.phase[j]) : F.amp[j] * exp(ph);
+    }
+  }
+  return v + p.R * t;
+}
+
+// phi*(x, 0) and its gradient.
+template <int D>
+__device__ void field_initial(const FieldDev& F, const KParams& p, const double (&x)[D],
+                              double& phi, double (&grad)[D]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) grad[a] = 0.0;
+  phi = 0.0;
+  if (F.kind == kFieldTanh) {
+    double y[D];
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      y[a] = x[a] - F.center[a];
+      r2 += y[a] * y[a];
+    }
+    const double r = sqrt(r2);
+    const double z = (F.Rr - r) / (2.0 * F.W);
+    phi = 0.5 - 0.5 * tanh(z);
+    const double ch = cosh(z);
+    const double dphi_dr = 0.5 / (ch * ch) / (2.0 * F.W);
+    if (r > 0.0) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) grad[a] = dphi_dr * y[a] / r;
+    }
+    return;
+  }
+  for (int j = 0; j < F.nmodes; ++j) {
+    double ph = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ph += F.kvec[j][a] * x[a];
+    if (F.kind == kFieldCos) {
+      double s, c;
+      sincos(ph + F.phase[j], &s, &c);
+      phi += F.amp[j] * c;
+#pragma unroll
+      for (int a = 0; a < D; ++a) grad[a] -= F.amp[j] * F.kvec[j][a] * s;
+    } else {
+      const double e = F.amp[j] * exp(ph);
+      phi += e;
+#pragma unroll
+      for (int a = 0; a < D; ++a) grad[a] += F.kvec[j][a] * e;
+    }
+  }
+}
+
+// --------------------------------------------------------- wall schemes -----
+//
+// The exact solution is phi*(x,t) = F(x - u t) + R t, so on one Fourier or
+// exponential mode every time derivative multiplies by w = -kappa.u and every
+// derivative along c_k by pc = kappa.c_k; derivatives of cos cycle through
+// cos, -sin, -cos, sin.
+//
+// Full-way, eq. (bun-1) at (x_b = node, t_{n+1}): with a = dt d_t and
+// b = dt c_k.grad the printed polynomial is 1 - (a+b)/2 + (a+b)^3/24 applied to
+// f^eq (its R terms cancel against the R t part), i.e. per mode
+//   omega_k [F - (dt/2) v.grad F + (dt^3/24) (v.grad)^3 F] + omega_k R t,
+// v = c_k - u; order 3 drops the cubic term, order 1 keeps F only.
+//
+// Half-way, eq. (bun2) at (x_b = x_f - c_k dx/2, t_n): the sum of
+//   (omega_k + omega_kbar) [1 + (dt/2) d_t - (dt^2/8)(c.grad)^2
+//                           - (dt^3/16)(c.grad)^2 d_t - (dt^3/24) d_t^3]
+//   (omega_k - omega_kbar) [-(dt^2/4) c.grad d_t - (dt^3/8) c.grad d_t^2]
+// applied to phi*, plus (dt/2)(R_k + R_kbar), truncated at order P; the new
+// population is that minus the post-collision f*_kbar at x_f.
+
+// Value of one unknown population at a wall node x (node coordinates, d
+// components): the absolute pre-collision f_k(x, t_{n+1}).  fbar_star is the
+// post-collision f*_kbar(x, t_n), used by the half-way scheme.  Kept out of
+// line: it runs for wall nodes only and must not inflate the register budget
+// of its caller.
+__device__ __noinline__ double wall_population(const KParams& p, int k, const double* x,
+                                               double t_n, double fbar_star) {
+  const FieldDev& F = p.field;
+  const int d = p.d;
+  const double dt = p.dt;
+  const bool full = p.scheme == kFullWay;
+  const bool is_cos = F.kind == kFieldCos;
+  const double o2 = p.P >= 2 ? 1.0 : 0.0;
+  const double o3 = p.P >= 3 ? 1.0 : 0.0;
+  const double o4 = p.P >= 4 ? 1.0 : 0.0;
+  const double dt2 = dt * dt, dt3 = dt2 * dt;
+  const int kb = p.kbar[k];
+  const double wp = p.omega[k] + p.omega[kb];
+  const double wm = p.omega[k] - p.omega[kb];
+  // full-way: x_b = x at t_{n+1};  half-way: x_b = x - c_k dx / 2 at t_n
+  const double t = full ? t_n + dt : t_n;
+  const double hshift = full ? 0.0 : 0.5 * p.dx;
+  double acc = 0.0;
+  for (int j = 0; j < F.nmodes; ++j) {
+    double ph = 0.0, pc = 0.0;
+    for (int a = 0; a < d; ++a) {
+      const double xb = x[a] - hshift * p.cv[k][a];
+      ph += F.kvec[j][a] * (xb - p.u[a] * t);
+      pc += p.cv[k][a] * F.kvec[j][a];
+    }
+    const double w = -F.ku[j];
+    double C = 0.0, S = 0.0, E = 0.0;
+    if (is_cos)
+      sincos(ph + F.phase[j], &S, &C);
+    else
+      E = exp(ph);
+    if (full) {
+      const double pv = pc + w;  // kappa . (c_k - u)
+      const double pv3 = pv * pv * pv;
+      if (is_cos)
+        acc += F.amp[j] * (C + (o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3) * S);
+      else
+        acc += F.amp[j] * E * (1.0 - o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3);
+    } else {
+      const double T0 = wp;
+      const double T1 = o2 * wp * 0.5 * dt * w;
+      const double T2 = -o3 * (wp * dt2 / 8.0 * pc * pc + wm * dt2 / 4.0 * pc * w);
+      const double T3 = -o4 * (wp * (dt3 / 16.0 * pc * pc * w + dt3 / 24.0 * w * w * w) +
+                               wm * dt3 / 8.0 * pc * w * w);
+      if (is_cos)
+        acc += F.amp[j] * ((T0 - T2) * C + (T3 - T1) * S);
+      else
+        acc += F.amp[j] * (T0 + T1 + T2 + T3) * E;
+    }
+  }
+  if (full) return p.omega[k] * (acc + p.R * t);
+  return -fbar_star + acc + wp * p.R * t_n + o2 * wp * p.R * dt;
+}
+
+template <int D, class A, class FStarLocal>
+__device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, const RowInfo<D>& r,
+                                            double t_n, double ref, FStarLocal fstar_local) {
+  double x[kMaxDim] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = p.origin[a] + (r.i[a] + p.shift[a]) * p.dx;
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    if (!outside<D, k>(r)) return;
+    constexpr int kb = opp_index(D, k);
+    const double fbs = (p.scheme == kHalfWay) ? fstar_local(kb) : 0.0;
+    const double val = wall_population(p, k, x, t_n, fbs);
+    f[k] = static_cast<A>(val - p.omega[k] * ref);
+  });
+}
+
+// ------------------------------------------------------------ step kernels --
+
+// Collision of the pulled pre-collision populations and store of the
+// post-collision ones.  float64: f*_k = (1-s) f_k + s omega_k phi + dt omega_k R.
+// float32 stores deviations from the uniform exact state omega_k (phi_ref + R t),
+// which is a fixed point of stream + collide, so the deviations follow the same
+// update without the source term; phi is summed with TwoSum compensation.
+template <int D, class T>
+__device__ __forceinline__ void collide_store(T (&f)[q_of(D)], T* __restrict__ dst, long long ps,
+                                              int node, const KParams& p) {
+  constexpr int Q = q_of(D);
+  if constexpr (std::is_same<T, float>::value) {
+    float sum = f[0], comp = 0.0f;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      float e;
+      two_sum(sum, f[k], sum, e);
+      comp += e;
+    }
+    const float phi = sum + comp;
+    const float oms = 1.0f - p.s_f;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) dst[k * ps + node] = fmaf(p.s_f * p.omega_f[k], phi, oms * f[k]);
+  } else {
+    double phi = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) phi += f[k];
+    const double oms = 1.0 - p.s;
+    const double dtR = p.dt * p.R;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      dst[k * ps + node] = fma(p.s * p.omega[k], phi, fma(oms, f[k], dtR * p.omega[k]));
+  }
+}
+
+// Bulk nodes: post-collision populations stored (float64, or float32
+// deviations).  Nodes on a Dirichlet wall are left to k_wall.
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_step(const T* __restrict__ src, T* __restrict__ dst, const KParams p) {
+  constexpr int Q = q_of(D);
+  const int row = blockIdx.x * blockDim.y + threadIdx.y;
+  if (row >= p.rows) return;
+  RowInfo<D> r;
+  row_setup<D>(p, row, r);
+  if (r.rowwall) return;
+  const long long ps = p.pstride;
+  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+    col_setup<D>(p, x, r);
+    if (r.lo[0] || r.hi[0]) continue;
+    const int node = r.rowbase + x;
+    T f[Q];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      f[k] = src[k * ps + node + pull_offset<D, k>(r)];
+    });
+    collide_store<D, T>(f, dst, ps, node, p);
+  }
+}
+
+// Split representation: phi (float64) and g_k = f_k - omega_k phi (float32),
+// pre-collision.  f*_k(y) = omega_k phi(y) + (1 - s) g_k(y) + dt omega_k R, so
+// the pull needs phi and g_k at the upwind node only; arithmetic is float64.
+template <int D>
+__device__ __forceinline__ void split_pull(double (&f)[q_of(D)], const float* __restrict__ gsrc,
+                                           const double* __restrict__ phisrc, long long ps,
+                                           int node, const RowInfo<D>& r, const KParams& p) {
+  const double oms = 1.0 - p.s;
+  const double dtR = p.dt * p.R;
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    const int idx = node + pull_offset<D, k>(r);
+    f[k] = fma(p.omega[k], phisrc[idx],
+               fma(oms, static_cast<double>(gsrc[k * ps + idx]), dtR * p.omega[k]));
+  });
+}
+
+template <int D>
+__device__ __forceinline__ void split_store(const double (&f)[q_of(D)], float* __restrict__ gdst,
+                                            double* __restrict__ phidst, long long ps, int node,
+                                            const KParams& p) {
+  constexpr int Q = q_of(D);
+  double phi = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) phi += f[k];
+  phidst[node] = phi;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) gdst[k * ps + node] = static_cast<float>(f[k] - p.omega[k] * phi);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256)
+    k_step_split(const float* __restrict__ gsrc, float* __restrict__ gdst,
+                 const double* __restrict__ phisrc, double* __restrict__ phidst, const KParams p) {
+  constexpr int Q = q_of(D);
+  const int row = blockIdx.x * blockDim.y + threadIdx.y;
+  if (row >= p.rows) return;
+  RowInfo<D> r;
+  row_setup<D>(p, row, r);
+  if (r.rowwall) return;
+  const long long ps = p.pstride;
+  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+    col_setup<D>(p, x, r);
+    if (r.lo[0] || r.hi[0]) continue;
+    const int node = r.rowbase + x;
+    double f[Q];
+    split_pull<D>(f, gsrc, phisrc, ps, node, r, p);
+    split_store<D>(f, gdst, phidst, ps, node, p);
+  }
+}
+
+// Wall nodes.  Face (a, side) lists the nodes with i_a at that side whose
+// indices on the Dirichlet axes b < a are interior, so every wall node is
+// visited exactly once.
+template <int D>
+__device__ __forceinline__ bool wall_node(const KParams& p, long long idx, RowInfo<D>& r) {
+  int f = 0;
+  while (f < p.nfaces && idx >= p.face_count[f]) {
+    idx -= p.face_count[f];
+    ++f;
+  }
+  if (f >= p.nfaces) return false;
+  const int a0 = p.face_axis[f];
+  long long l = idx;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    if (b == a0) {
+      r.i[b] = p.face_side[f] ? p.n[b] - 1 : 0;
+      continue;
+    }
+    const bool inner = (b < a0) && p.bc[b] != 0;
+    const int nb = inner ? p.n[b] - 2 : p.n[b];
+    r.i[b] = static_cast<int>(l % nb) + (inner ? 1 : 0);
+    l /= nb;
+  }
+  int node = 0;
+  r.rowwall = false;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const int n = p.n[b];
+    const int st = p.stride[b];
+    const int ib = r.i[b];
+    node += ib * st;
+    r.dm[b] = (ib == 0) ? (n - 1) * st : -st;
+    r.dp[b] = (ib == n - 1) ? -(n - 1) * st : st;
+    const bool wall = p.bc[b] != 0;
+    r.lo[b] = wall && ib == 0;
+    r.hi[b] = wall && ib == n - 1;
+  }
+  r.rowbase = node;  // node index of this wall node
+  return true;
+}
+
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_wall(const T* __restrict__ src, T* __restrict__ dst, const KParams p, const double t_n) {
+  constexpr int Q = q_of(D);
+  constexpr bool kF32 = std::is_same<T, float>::value;
+  const long long ps = p.pstride;
+  // reference of the float32 deviations at t_{n+1}
+  const double ref = kF32 ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < p.wall_nodes;
+       idx += (long long)gridDim.x * blockDim.x) {
+    RowInfo<D> r;
+    if (!wall_node<D>(p, idx, r)) continue;
+    const int node = r.rowbase;
+    T f[Q];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      f[k] = src[k * ps + node + pull_offset<D, k>(r)];
+    });
+    wall_values<D, T>(f, p, r, t_n, ref, [&](int kb) {
+      return static_cast<double>(src[kb * ps + node]) + p.omega[kb] * ref;
+    });
+    collide_store<D, T>(f, dst, ps, node, p);
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256)
+    k_wall_split(const float* __restrict__ gsrc, float* __restrict__ gdst,
+                 const double* __restrict__ phisrc, double* __restrict__ phidst, const KParams p,
+                 const double t_n) {
+  constexpr int Q = q_of(D);
+  const long long ps = p.pstride;
+  const double oms = 1.0 - p.s;
+  const double dtR = p.dt * p.R;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < p.wall_nodes;
+       idx += (long long)gridDim.x * blockDim.x) {
+    RowInfo<D> r;
+    if (!wall_node<D>(p, idx, r)) continue;
+    const int node = r.rowbase;
+    double f[Q];
+    split_pull<D>(f, gsrc, phisrc, ps, node, r, p);
+    wall_values<D, double>(f, p, r, t_n, 0.0, [&](int kb) {
+      return fma(p.omega[kb], phisrc[node],
+                 fma(oms, static_cast<double>(gsrc[kb * ps + node]), dtR * p.omega[kb]));
+    });
+    split_store<D>(f, gdst, phidst, ps, node, p);
+  }
+}
+
+// ------------------------------------------------------------ node helpers --
+
+template <int D>
+__device__ __forceinline__ void node_index(const KParams& p, int node, int (&i)[D]) {
+  int rr = node;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    i[a] = rr % p.n[a];
+    rr /= p.n[a];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void node_coords(const KParams& p, const int (&i)[D], double (&x)[D]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = p.origin[a] + (i[a] + p.shift[a]) * p.dx;
+}
+
+// ------------------------------------------------------------------ init ----
+
+template <int D>
+__device__ double fd4_derivative(const double* phi, const KParams& p, const int (&i)[D], int node,
+                                 int a) {
+  const int n = p.n[a];
+  const int st = p.stride[a];
+  auto at = [&](int s) {
+    int j = i[a] + s;
+    j = (j % n + n) % n;
+    return phi[node + (j - i[a]) * st];
+  };
+  return (-at(2) + 8.0 * at(1) - 8.0 * at(-1) + at(-2)) / (12.0 * p.dx);
+}
+
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_init(T* __restrict__ dst, double* __restrict__ phidst, const double* __restrict__ phi0,
+           const double* __restrict__ grad0, const KParams p, int mode) {
+  constexpr int Q = q_of(D);
+  const long long ps = p.pstride;
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
+       node += gridDim.x * blockDim.x) {
+    int i[D];
+    node_index<D>(p, node, i);
+    double phi, grad[D];
+    if (phi0 == nullptr) {
+      double x[D];
+      node_coords<D>(p, i, x);
+      field_initial<D>(p.field, p, x, phi, grad);
+    } else {
+      phi = phi0[node];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        grad[a] = (p.K == 3) ? (grad0 ? grad0[(long long)a * p.nodes + node]
+                                      : fd4_derivative<D>(phi0, p, i, node, a))
+                             : 0.0;
+    }
+    // f_k = omega_k [phi0 + tau dt (u - c_k) . grad phi0]  (eq. ini-simp at tau = 1/2)
+    double f[Q];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr Vec4i c = vel_vec(D, k);
+      double dir = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) dir += (p.u[a] - c.v[a]) * grad[a];
+      f[k] = p.omega[k] * (p.K == 3 ? phi + p.tau * p.dt * dir : phi);
+    });
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) sum += f[k];
+    if (mode == kSplit) {
+      phidst[node] = sum;
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        reinterpret_cast<float*>(dst)[k * ps + node] = static_cast<float>(f[k] - p.omega[k] * sum);
+    } else {
+      // post-collision state at t_0; float32 stores the deviation from
+      // omega_k (phi_ref + R t_1)
+      const double ref = (mode == kFP32) ? p.phi_ref + p.R * p.dt : 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const double fs = (1.0 - p.s) * f[k] + p.s * p.omega[k] * sum + p.dt * p.omega[k] * p.R;
+        dst[k * ps + node] = static_cast<T>(fs - p.omega[k] * ref);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------- moments ----
+
+__device__ __forceinline__ void block_reduce(double (&v)[kNumAcc], double* sh) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < kNumAcc; ++m) sh[m * kRedThreads + tid] = v[m];
+  __syncthreads();
+  for (int half = kRedThreads / 2; half > 0; half >>= 1) {
+    if (tid < half) {
+#pragma unroll
+      for (int m = 0; m < kNumAcc; ++m) {
+        const double a = sh[m * kRedThreads + tid], b = sh[m * kRedThreads + tid + half];
+        sh[m * kRedThreads + tid] = (m == 4) ? fmax(a, b) : a + b;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < kNumAcc; ++m) v[m] = sh[m * kRedThreads];
+}
+
+// accumulators: 0 sum phi, 1 sum phi^2, 2 sum (phi - phi*)^2,
+// 3 sum_k f_k^2 / (2 omega_k), 4 max |phi|, 5 non-finite count
+template <int D, class T>
+__global__ void __launch_bounds__(kRedThreads)
+    k_moments(const T* __restrict__ f, const double* __restrict__ phis, const KParams p,
+              const int mode, const double t_n, double* __restrict__ phi_out,
+              double* __restrict__ partial) {
+  constexpr int Q = q_of(D);
+  __shared__ double sh[kNumAcc * kRedThreads];
+  double acc[kNumAcc] = {0, 0, 0, 0, 0, 0};
+  const long long ps = p.pstride;
+  const bool has_field = p.field.kind != kFieldNone;
+  const double ref = (mode == kFP32) ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
+       node += gridDim.x * blockDim.x) {
+    double fk[Q];
+    double phi;
+    if (mode == kSplit) {
+      phi = phis[node];
+      const float* g = reinterpret_cast<const float*>(f);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) fk[k] = static_cast<double>(g[k * ps + node]) + p.omega[k] * phi;
+    } else {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        fk[k] = static_cast<double>(f[k * ps + node]) + p.omega[k] * ref;
+        sum += fk[k];
+      }
+      phi = sum - p.dt * p.R;
+      // pre-collision populations from the post-collision ones (s != 1)
+      const double inv = 1.0 / (1.0 - p.s);
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        fk[k] = (fk[k] - p.dt * p.omega[k] * p.R - p.s * p.omega[k] * phi) * inv;
+    }
+    double ent = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ent += fk[k] * fk[k] / (2.0 * p.omega[k]);
+    if (phi_out) phi_out[node] = phi;
+    acc[0] += phi;
+    acc[1] += phi * phi;
+    if (has_field) {
+      int i[D];
+      double x[D];
+      node_index<D>(p, node, i);
+      node_coords<D>(p, i, x);
+      const double e = phi - field_value<D>(p.field, p, x, t_n);
+      acc[2] += e * e;
+    }
+    acc[3] += ent;
+    acc[4] = fmax(acc[4], fabs(phi));
+    acc[5] += isfinite(phi) ? 0.0 : 1.0;
+  }
+  block_reduce(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < kNumAcc; ++m) partial[blockIdx.x * kNumAcc + m] = acc[m];
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kRedThreads)
+    k_sum_phi0(const double* __restrict__ arr, const KParams p, double* __restrict__ partial) {
+  __shared__ double sh[kNumAcc * kRedThreads];
+  double acc[kNumAcc] = {0, 0, 0, 0, 0, 0};
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
+       node += gridDim.x * blockDim.x) {
+    double v;
+    if (arr) {
+      v = arr[node];
+    } else {
+      int i[D];
+      double x[D], g[D];
+      node_index<D>(p, node, i);
+      node_coords<D>(p, i, x);
+      field_initial<D>(p.field, p, x, v, g);
+    }
+    acc[0] += v;
+  }
+  block_reduce(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < kNumAcc; ++m) partial[blockIdx.x * kNumAcc + m] = acc[m];
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+    k_reduce_final(const double* __restrict__ partial, int nblocks, double* __restrict__ out) {
+  __shared__ double sh[kNumAcc * kRedThreads];
+  double acc[kNumAcc] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+    for (int m = 0; m < kNumAcc; ++m) {
+      const double v = partial[b * kNumAcc + m];
+      acc[m] = (m == 4) ? fmax(acc[m], v) : acc[m] + v;
+    }
+  }
+  block_reduce(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < kNumAcc; ++m) out[m] = acc[m];
+  }
+}
+
+// ------------------------------------------------------------- launchers ----
+
+LaunchShape step_shape(const KParams& p) {
+  int tx = 64;
+  while (tx < p.n[0] && tx < 256) tx *= 2;
+  const int ty = 256 / tx;
+  LaunchShape s;
+  s.tx = tx;
+  s.ty = ty;
+  s.blocks = static_cast<unsigned>((p.rows + ty - 1) / ty);
+  return s;
+}
+
+static unsigned grid_for(long long nodes, int threads) {
+  long long b = (nodes + threads - 1) / threads;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return static_cast<unsigned>(b);
+}
+
+template <int D>
+static hipError_t step_d(const KParams& p, int mode, const void* src, void* dst,
+                         const double* phi_src, double* phi_dst, long long n,
+                         hipStream_t stream) {
+  const LaunchShape s = step_shape(p);
+  const dim3 block(s.tx, s.ty), grid(s.blocks);
+  const double t_n = static_cast<double>(n) * p.dt;
+  const dim3 wblock(256), wgrid(grid_for(p.wall_nodes, 256));
+  if (mode == kFP64) {
+    auto* a = static_cast<const double*>(src);
+    auto* b = static_cast<double*>(dst);
+    hipLaunchKernelGGL((k_step<D, double>), grid, block, 0, stream, a, b, p);
+    if (p.wall_nodes > 0)
+      hipLaunchKernelGGL((k_wall<D, double>), wgrid, wblock, 0, stream, a, b, p, t_n);
+  } else if (mode == kFP32) {
+    auto* a = static_cast<const float*>(src);
+    auto* b = static_cast<float*>(dst);
+    hipLaunchKernelGGL((k_step<D, float>), grid, block, 0, stream, a, b, p);
+    if (p.wall_nodes > 0)
+      hipLaunchKernelGGL((k_wall<D, float>), wgrid, wblock, 0, stream, a, b, p, t_n);
+  } else {
+    auto* a = static_cast<const float*>(src);
+    auto* b = static_cast<float*>(dst);
+    hipLaunchKernelGGL((k_step_split<D>), grid, block, 0, stream, a, b, phi_src, phi_dst, p);
+    if (p.wall_nodes > 0)
+      hipLaunchKernelGGL((k_wall_split<D>), wgrid, wblock, 0, stream, a, b, phi_src, phi_dst, p,
+                         t_n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const KParams& p, int mode, const void* src, void* dst,
+                       const double* phi_src, double* phi_dst, long long n,
+                       hipStream_t stream) {
+  switch (p.d) {
+    case 1: return step_d<1>(p, mode, src, dst, phi_src, phi_dst, n, stream);
+    case 2: return step_d<2>(p, mode, src, dst, phi_src, phi_dst, n, stream);
+    case 3: return step_d<3>(p, mode, src, dst, phi_src, phi_dst, n, stream);
+    case 4: return step_d<4>(p, mode, src, dst, phi_src, phi_dst, n, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+
+template <int D>
+static hipError_t init_d(const KParams& p, int mode, void* dst, double* phi_dst,
+                         const double* phi0, const double* grad0, hipStream_t stream) {
+  const dim3 block(256), grid(grid_for(p.nodes, 256));
+  if (mode == kFP64)
+    hipLaunchKernelGGL((k_init<D, double>), grid, block, 0, stream, static_cast<double*>(dst),
+                       phi_dst, phi0, grad0, p, mode);
+  else
+    hipLaunchKernelGGL((k_init<D, float>), grid, block, 0, stream, static_cast<float*>(dst),
+                       phi_dst, phi0, grad0, p, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const KParams& p, int mode, void* dst, double* phi_dst,
+                       const double* phi0, const double* grad0, hipStream_t stream) {
+  switch (p.d) {
+    case 1: return init_d<1>(p, mode, dst, phi_dst, phi0, grad0, stream);
+    case 2: return init_d<2>(p, mode, dst, phi_dst, phi0, grad0, stream);
+    case 3: return init_d<3>(p, mode, dst, phi_dst, phi0, grad0, stream);
+    case 4: return init_d<4>(p, mode, dst, phi_dst, phi0, grad0, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int D>
+static hipError_t moments_d(const KParams& p, int mode, const void* f, const double* phi,
+                            long long n, double* phi_out, double* partial, double* out,
+                            hipStream_t stream) {
+  const double t_n = static_cast<double>(n) * p.dt;
+  const dim3 block(kRedThreads), grid(kRedBlocks);
+  if (mode == kFP64)
+    hipLaunchKernelGGL((k_moments<D, double>), grid, block, 0, stream,
+                       static_cast<const double*>(f), phi, p, mode, t_n, phi_out, partial);
+  else
+    hipLaunchKernelGGL((k_moments<D, float>), grid, block, 0, stream,
+                       static_cast<const float*>(f), phi, p, mode, t_n, phi_out, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, stream, partial, kRedBlocks,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const KParams& p, int mode, const void* f, const double* phi,
+                          long long n, double* phi_out, double* partial, double* out,
+                          hipStream_t stream) {
+  switch (p.d) {
+    case 1: return moments_d<1>(p, mode, f, phi, n, phi_out, partial, out, stream);
+    case 2: return moments_d<2>(p, mode, f, phi, n, phi_out, partial, out, stream);
+    case 3: return moments_d<3>(p, mode, f, phi, n, phi_out, partial, out, stream);
+    case 4: return moments_d<4>(p, mode, f, phi, n, phi_out, partial, out, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int D>
+static hipError_t sum_phi0_d(const KParams& p, const double* arr, double* partial, double* out,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL((k_sum_phi0<D>), dim3(kRedBlocks), dim3(kRedThreads), 0, stream, arr, p,
+                     partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, stream, partial, kRedBlocks,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_phi0(const KParams& p, const double* arr, double* partial, double* out,
+                           hipStream_t stream) {
+  switch (p.d) {
+    case 1: return sum_phi0_d<1>(p, arr, partial, out, stream);
+    case 2: return sum_phi0_d<2>(p, arr, partial, out, stream);
+    case 3: return sum_phi0_d<3>(p, arr, partial, out, stream);
+    case 4: return sum_phi0_d<4>(p, arr, partial, out, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,86 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the examples.
+
+Only parameter draws live here (field amplitudes, wave vectors, phases,
+velocities, noise); nothing of the lattice Boltzmann method itself.  Each
+workload returns plain dicts that both the GPU binding and the CPU oracle
+accept.
+"""
+from __future__ import annotations
+
+import math
+from typing import Sequence
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+def plane_sine(d: int, u: Sequence[float], R: float = 0.0) -> dict:
+    """phi0 = prod_i sin(2 pi x_i) written as a sum of cosines (exact in 1-3D)."""
+    if d == 1:
+        modes = [(1.0, [TWO_PI], -math.pi / 2)]
+    elif d == 2:
+        # sin a sin b = (cos(a - b) - cos(a + b)) / 2
+        modes = [(0.5, [TWO_PI, -TWO_PI], 0.0), (-0.5, [TWO_PI, TWO_PI], 0.0)]
+    elif d == 3:
+        # sin a sin b sin c = (sin(a+b-c) + sin(a-b+c) + sin(-a+b+c) - sin(a+b+c)) / 4
+        modes = []
+        for sgn, amp in (((1, 1, -1), 0.25), ((1, -1, 1), 0.25), ((-1, 1, 1), 0.25),
+                         ((1, 1, 1), -0.25)):
+            modes.append((amp, [TWO_PI * s for s in sgn], -math.pi / 2))
+    else:
+        raise ValueError("plane_sine is defined for d <= 3")
+    return {"kind": "cos_sum", "amps": [m[0] for m in modes], "kvecs": [m[1] for m in modes],
+            "phases": [m[2] for m in modes], "u": list(u), "R": R}
+
+
+def diagonal_sine(d: int, u: Sequence[float], k: float = math.pi) -> dict:
+    """Example 3: phi* = sin[pi (sum_i x_i - u_i t)]."""
+    return {"kind": "cos_sum", "amps": [1.0], "kvecs": [[k] * d], "phases": [-math.pi / 2],
+            "u": list(u), "R": 0.0}
+
+
+def example1(u: Sequence[float], R: float = 5.0) -> dict:
+    """Example 1: exp[-(x1 - u1 t) - (x2 - u2 t)] + R t."""
+    return {"kind": "exp_sum", "amps": [1.0], "kvecs": [[-1.0, -1.0]], "phases": [0.0],
+            "u": list(u), "R": R}
+
+
+def tanh_bubble(d: int, u: Sequence[float]) -> dict:
+    """Example 2: 1/2 - 1/2 tanh((Rr - |x - u t|)/(2W)), Rr = 1/(5(d-1)), W = (5-d)/75."""
+    return {"kind": "tanh_bubble", "Rr": 1.0 / (5.0 * (d - 1)), "W": (5.0 - d) / 75.0,
+            "center": [0.0] * d, "u": list(u), "R": 0.0}
+
+
+def random_cosines(d: int, u: Sequence[float], R: float, seed: int, n_modes: int = 4,
+                   kmax: float = 3.0) -> dict:
+    """Sum of n random-wavevector cosines: a_j ~ N(0,1), kappa_j = 2 pi U(-kmax, kmax)^d,
+    theta_j ~ U[0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    amps = rng.normal(size=n_modes)
+    kv = TWO_PI * rng.uniform(-kmax, kmax, size=(n_modes, d))
+    ph = rng.uniform(0.0, TWO_PI, size=n_modes)
+    return {"kind": "cos_sum", "amps": amps.tolist(), "kvecs": kv.tolist(),
+            "phases": ph.tolist(), "u": list(u), "R": R}
+
+
+def tau_draw(seed: int, lo: float, hi: float) -> float:
+    return float(np.random.default_rng(seed).uniform(lo, hi))
+
+
+def noise(shape: Sequence[int], seed: int, std: float = 1e-3) -> np.ndarray:
+    """i.i.d. N(0, std^2) values, float64, C order of the given shape."""
+    return np.random.default_rng(seed).normal(0.0, std, size=tuple(shape))
+
+
+# Workload of the benchmark: D3Q19 on the unit cube, 512 nodes per axis,
+# full-way Dirichlet walls on all six faces with data from four random cosines
+# (seed 3), u = (0.05, 0.1, 0.08) (Table 3), R = 1, K = 3, P = 4.
+BENCH_D3Q19 = {
+    "d": 3, "n": 512, "u": [0.05, 0.1, 0.08], "R": 1.0, "seed": 3, "steps": 2000,
+}
+
+
+def bench_field() -> dict:
+    w = BENCH_D3Q19
+    return random_cosines(3, w["u"], w["R"], w["seed"])

@@ -1,0 +1,325 @@
+"""Thin ctypes binding of liblbm.so (include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  PyTorch supplies the device memory (through the allocator
+callbacks of lbm_params) and the stream (the current torch stream at creation).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+MAX_DIM = 4
+MAX_Q = 33
+MAX_MODES = 16
+NSCALARS = 8
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5
+BC = {"periodic": 0, "fullway": 1, "halfway": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_split": 2}
+FIELD = {"none": 0, "cos_sum": 1, "exp_sum": 2, "tanh_bubble": 3}
+
+_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class LbmField(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("n_modes", C.c_int32),
+        ("amps", C.POINTER(C.c_double)), ("kvecs", C.POINTER(C.c_double)),
+        ("phases", C.POINTER(C.c_double)),
+        ("Rr", C.c_double), ("W", C.c_double), ("center", C.c_double * MAX_DIM),
+    ]
+
+
+class LbmParams(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("dx", C.c_double), ("origin", C.c_double * MAX_DIM), ("u", C.c_double * MAX_DIM),
+        ("R", C.c_double), ("g", C.c_double), ("m4", C.c_double), ("use_m4", C.c_int32),
+        ("bc", C.c_int32 * MAX_DIM), ("bc_order", C.c_int32), ("init_order", C.c_int32),
+        ("precision", C.c_int32), ("field", C.POINTER(LbmField)),
+        ("alloc", _ALLOC), ("free_fn", _FREE), ("alloc_ctx", C.c_void_p),
+        ("stream", C.c_void_p),
+    ]
+
+
+class LbmInfo(C.Structure):
+    _fields_ = [
+        ("d", C.c_int32), ("q", C.c_int32), ("precision", C.c_int32),
+        ("entropy_stable", C.c_int32),
+        ("dims", C.c_int64 * MAX_DIM), ("nodes", C.c_int64), ("step", C.c_int64),
+        ("omega", C.c_double * MAX_Q), ("m4", C.c_double), ("min_omega", C.c_double),
+        ("s", C.c_double), ("dt", C.c_double), ("phi_ref", C.c_double),
+        ("bytes_per_lu", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+# exported symbols and their signatures, as declared in include/lbm.h
+SIGNATURES = {
+    "lbm_params_default": (None, [C.POINTER(LbmParams)]),
+    "lbm_create": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.c_double, C.POINTER(LbmParams),
+                             C.POINTER(C.c_void_p)]),
+    "lbm_set_initial": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "lbm_info": (C.c_int, [C.c_void_p, C.POINTER(LbmInfo)]),
+    "lbm_state_bytes": (C.c_int64, [C.c_void_p]),
+    "lbm_get_state": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lbm_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "lbm_equilibrium_weights": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.c_double, C.c_int,
+                                           C.c_double, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lbm_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_destroy": (C.c_int, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load liblbm.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_2410_13165_amd.build` "
+            "(there is no CPU fallback)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def equilibrium_weights(u: Sequence[float], g: float = 0.5, m4: Optional[float] = None):
+    """(omega, m4, min_omega) from the library's host maths (no GPU needed)."""
+    lib = load_library()
+    d = len(u)
+    uu = (C.c_double * max(MAX_DIM, d))(*[float(v) for v in u])
+    om = (C.c_double * MAX_Q)()
+    m4o = C.c_double()
+    mn = C.c_double()
+    rc = lib.lbm_equilibrium_weights(d, uu, float(g), 1 if m4 is not None else 0,
+                                     float(m4) if m4 is not None else 0.0, om,
+                                     C.byref(m4o), C.byref(mn))
+    if rc != OK:
+        raise LbmError(rc, lib.lbm_last_error(None).decode())
+    return np.array(om[: 2 * d * d + 1]), m4o.value, mn.value
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+@dataclass
+class Field:
+    """Analytic solution phi*(x,t) = F(x - u t) + R t (see include/lbm.h)."""
+    kind: str
+    amps: Sequence[float] = ()
+    kvecs: Sequence[Sequence[float]] = ()
+    phases: Optional[Sequence[float]] = None
+    Rr: float = 0.0
+    W: float = 1.0
+    center: Optional[Sequence[float]] = None
+
+    @classmethod
+    def from_dict(cls, spec: dict) -> "Field":
+        return cls(kind=spec["kind"], amps=spec.get("amps", ()), kvecs=spec.get("kvecs", ()),
+                   phases=spec.get("phases"), Rr=spec.get("Rr", 0.0), W=spec.get("W", 1.0),
+                   center=spec.get("center"))
+
+
+class Lattice:
+    """One lattice of the fourth-order BGK model on the current CUDA/HIP device.
+
+    dims = (N_1, ..., N_d); bc = one of "periodic", "fullway", "halfway" per axis.
+    """
+
+    def __init__(self, d: int, dims: Sequence[int], tau: float = 0.5, *, dx: float,
+                 u: Sequence[float], R: float = 0.0, origin: Optional[Sequence[float]] = None,
+                 bc: Optional[Sequence[str]] = None, P: int = 4, K: int = 3,
+                 precision: str = "fp64", field=None, g: float = 0.5,
+                 m4: Optional[float] = None, device=None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.type != "cuda":
+            raise ValueError("the lattice lives on a GPU device")
+        self.d = int(d)
+        self.dims = tuple(int(n) for n in dims)
+        self._bufs = {}
+        self._h = None
+        self._closed = False
+
+        p = LbmParams()
+        self.lib.lbm_params_default(C.byref(p))
+        p.dx = float(dx)
+        for a in range(self.d):
+            p.origin[a] = float(origin[a]) if origin is not None else 0.0
+            p.u[a] = float(u[a])
+            p.bc[a] = BC[bc[a]] if bc is not None else 0
+        p.R = float(R)
+        p.g = float(g)
+        if m4 is not None:
+            p.m4 = float(m4)
+            p.use_m4 = 1
+        p.bc_order = int(P)
+        p.init_order = int(K)
+        p.precision = PRECISION[precision]
+        self.precision = precision
+
+        self._field_keep = []
+        if field is not None:
+            if isinstance(field, dict):
+                field = Field.from_dict(field)
+            f = LbmField()
+            f.kind = FIELD[field.kind]
+            if field.kind in ("cos_sum", "exp_sum"):
+                amps = np.ascontiguousarray(field.amps, dtype=np.float64)
+                kv = np.ascontiguousarray(field.kvecs, dtype=np.float64).reshape(len(amps), self.d)
+                ph = np.ascontiguousarray(field.phases if field.phases is not None
+                                          else np.zeros(len(amps)), dtype=np.float64)
+                f.n_modes = len(amps)
+                f.amps = amps.ctypes.data_as(C.POINTER(C.c_double))
+                f.kvecs = kv.ctypes.data_as(C.POINTER(C.c_double))
+                f.phases = ph.ctypes.data_as(C.POINTER(C.c_double))
+                self._field_keep += [amps, kv, ph]
+            f.Rr = float(field.Rr)
+            f.W = float(field.W)
+            if field.center is not None:
+                for a in range(self.d):
+                    f.center[a] = float(field.center[a])
+            self._field_keep.append(f)
+            p.field = C.pointer(f)
+
+        # torch supplies the device memory
+        def _alloc(nbytes, ctx):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            except RuntimeError:
+                return None
+            ptr = t.data_ptr()
+            self._bufs[ptr] = t
+            return ptr
+
+        def _free(ptr, ctx):
+            self._bufs.pop(ptr, None)
+
+        self._alloc_cb = _ALLOC(_alloc)
+        self._free_cb = _FREE(_free)
+        p.alloc = self._alloc_cb
+        p.free_fn = self._free_cb
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        p.stream = C.c_void_p(self.stream.cuda_stream)
+        self._params = p
+
+        dims_arr = (C.c_int64 * MAX_DIM)(*(list(self.dims) + [1] * (MAX_DIM - self.d)))
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.lbm_create(self.d, dims_arr, float(tau), C.byref(p), C.byref(h))
+        if rc != OK:
+            raise LbmError(rc, self.lib.lbm_last_error(None).decode())
+        self._h = h
+
+    # ------------------------------------------------------------------ ABI
+    def _check(self, rc: int):
+        if rc != OK:
+            raise LbmError(rc, self.lib.lbm_last_error(self._h).decode())
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    @property
+    def nodes(self) -> int:
+        return int(np.prod(self.dims))
+
+    def set_initial(self, phi0, grad0=None):
+        torch = self._torch
+        phi0 = phi0.to(device=self.device, dtype=torch.float64).contiguous()
+        g = None
+        if grad0 is not None:
+            g = grad0.to(device=self.device, dtype=torch.float64).contiguous()
+        self._check(self.lib.lbm_set_initial(self._h, C.c_void_p(phi0.data_ptr()),
+                                             C.c_void_p(g.data_ptr()) if g is not None else None))
+        # keep the inputs alive until the stream has consumed them
+        self._init_keep = (phi0, g)
+        return self
+
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm_step(self._h, int(n)))
+        return self
+
+    def phi(self):
+        """phi(x, t_n) as a float64 tensor shaped (N_d, ..., N_1)."""
+        torch = self._torch
+        out = torch.empty(self.nodes, dtype=torch.float64, device=self.device)
+        self._check(self.lib.lbm_moments(self._h, C.c_void_p(out.data_ptr()), None))
+        return out.view(*reversed(self.dims))
+
+    def diagnostics(self) -> dict:
+        vals = (C.c_double * NSCALARS)()
+        self._check(self.lib.lbm_moments(self._h, None, vals))
+        keys = ("sum_phi", "sum_phi2", "sum_err2", "entropy", "max_abs_phi", "nonfinite",
+                "rmse", "t")
+        return {k: float(v) for k, v in zip(keys, vals)}
+
+    def info(self) -> dict:
+        inf = LbmInfo()
+        self._check(self.lib.lbm_info(self._h, C.byref(inf)))
+        return {
+            "d": inf.d, "q": inf.q, "precision": inf.precision,
+            "entropy_stable": bool(inf.entropy_stable),
+            "dims": tuple(inf.dims[: inf.d]), "nodes": inf.nodes, "step": inf.step,
+            "omega": np.array(inf.omega[: inf.q]), "m4": inf.m4, "min_omega": inf.min_omega,
+            "s": inf.s, "dt": inf.dt, "phi_ref": inf.phi_ref, "bytes_per_lu": inf.bytes_per_lu,
+        }
+
+    def state_bytes(self) -> int:
+        return int(self.lib.lbm_state_bytes(self._h))
+
+    def get_state(self):
+        torch = self._torch
+        buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.lbm_get_state(self._h, C.c_void_p(buf.data_ptr())))
+        return buf
+
+    def set_state(self, buf, step: int):
+        self._check(self.lib.lbm_set_state(self._h, C.c_void_p(buf.data_ptr()), int(step)))
+        self._state_keep = buf
+        return self
+
+    def close(self):
+        if self._h is not None and not self._closed:
+            self._closed = True
+            self.lib.lbm_destroy(self._h)
+            self._h = None
+            self._bufs.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,164 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/lbm.h, its structs have the layout the
+binding assumes, argument errors are reported before any device work, and the
+host maths of the weights agree with the oracle."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2410_13165_amd import lbm as B
+from oracle import lbm_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_binding_functions():
+    assert set(_declared_functions()) == set(B.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load_library()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (lbm_[a-z_]+)", out))
+    assert set(_declared_functions()) <= exported
+
+
+_LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "lbm.h"
+#define P(T, f) printf(#T " " #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("lbm_params size %zu\n", sizeof(lbm_params));
+  printf("lbm_field size %zu\n", sizeof(lbm_field));
+  printf("lbm_info_t size %zu\n", sizeof(lbm_info_t));
+  P(lbm_params, dx); P(lbm_params, origin); P(lbm_params, u); P(lbm_params, R);
+  P(lbm_params, g); P(lbm_params, m4); P(lbm_params, use_m4); P(lbm_params, bc);
+  P(lbm_params, bc_order); P(lbm_params, init_order); P(lbm_params, precision);
+  P(lbm_params, field); P(lbm_params, alloc); P(lbm_params, free_fn);
+  P(lbm_params, alloc_ctx); P(lbm_params, stream);
+  P(lbm_field, n_modes); P(lbm_field, amps); P(lbm_field, kvecs); P(lbm_field, phases);
+  P(lbm_field, Rr); P(lbm_field, W); P(lbm_field, center);
+  P(lbm_info_t, dims); P(lbm_info_t, nodes); P(lbm_info_t, step); P(lbm_info_t, omega);
+  P(lbm_info_t, m4); P(lbm_info_t, min_omega); P(lbm_info_t, s); P(lbm_info_t, dt);
+  P(lbm_info_t, phi_ref); P(lbm_info_t, bytes_per_lu);
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_header():
+    with tempfile.TemporaryDirectory() as tmp:
+        src = os.path.join(tmp, "layout.c")
+        exe = os.path.join(tmp, "layout")
+        open(src, "w").write(_LAYOUT_C)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe],
+                       check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    py = {"lbm_params": B.LbmParams, "lbm_field": B.LbmField, "lbm_info_t": B.LbmInfo}
+    for line in out.splitlines():
+        sname, field, val = line.split()
+        if field == "size":
+            assert C.sizeof(py[sname]) == int(val), sname
+        else:
+            assert getattr(py[sname], field).offset == int(val), (sname, field)
+
+
+def test_params_default():
+    lib = B.load_library()
+    p = B.LbmParams()
+    lib.lbm_params_default(C.byref(p))
+    assert p.struct_size == C.sizeof(B.LbmParams)
+    assert p.dx == 1.0 and p.g == 0.5 and p.bc_order == 4 and p.init_order == 3
+    assert p.precision == 0 and list(p.bc) == [0, 0, 0, 0]
+
+
+def _create(d, dims, tau, **kw):
+    lib = B.load_library()
+    p = B.LbmParams()
+    lib.lbm_params_default(C.byref(p))
+    for k, v in kw.items():
+        if k == "bc":
+            for a, b in enumerate(v):
+                p.bc[a] = b
+        else:
+            setattr(p, k, v)
+    arr = (C.c_int64 * 4)(*(list(dims) + [1] * (4 - len(dims))))
+    h = C.c_void_p()
+    rc = lib.lbm_create(d, arr, tau, C.byref(p), C.byref(h))
+    return rc, h, lib.lbm_last_error(None).decode()
+
+
+@pytest.mark.parametrize("args,code,msg", [
+    ((0, (4,), 0.5), B.EINVAL, "d must be"),
+    ((5, (4,) * 4, 0.5), B.EINVAL, "d must be"),
+    ((2, (4, 4), 0.0), B.EINVAL, "tau"),
+    ((2, (4, 4), -1.0), B.EINVAL, "tau"),
+    ((2, (0, 4), 0.5), B.EINVAL, "dims"),
+    ((3, (2048, 2048, 1024), 0.5), B.EINVAL, "2^31"),
+])
+def test_create_rejects_bad_arguments(args, code, msg):
+    rc, h, err = _create(*args)
+    assert rc == code and not h.value and msg in err
+
+
+def test_create_rejects_walls_without_field_and_mixed_schemes():
+    rc, h, err = _create(2, (8, 8), 0.5, bc=[1, 1])
+    assert rc == B.EINVAL and "field" in err
+    rc, h, err = _create(2, (8, 8), 0.5, bc=[1, 2])
+    assert rc == B.EUNSUPPORTED and "mixed" in err
+    rc, h, err = _create(2, (1, 8), 0.5, bc=[1, 0])
+    assert rc == B.EINVAL and "2 nodes" in err
+    rc, h, err = _create(2, (8, 8), 0.5, init_order=2)
+    assert rc == B.EINVAL and "init_order" in err
+    rc, h, err = _create(2, (8, 8), 0.5, dx=0.0)
+    assert rc == B.EINVAL and "dx" in err
+
+
+def test_null_handle_calls_fail_cleanly():
+    lib = B.load_library()
+    assert lib.lbm_step(None, 1) == B.EINVAL
+    assert lib.lbm_moments(None, None, None) == B.EINVAL
+    assert lib.lbm_destroy(None) == B.OK
+    assert lib.lbm_state_bytes(None) == -1
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_host_weights_match_oracle(d):
+    """The library's closed-form weights (eq. omega_k-2 with eq. meq-4rd) against
+    the oracle's M^{-1} eps."""
+    rng = np.random.default_rng(70 + d)
+    for _ in range(25):
+        u = rng.uniform(-0.6, 0.6, d)
+        w, m4, mn = B.equilibrium_weights(u)
+        np.testing.assert_allclose(w, O.omega(u), rtol=0, atol=1e-14)
+        if d >= 2:
+            assert abs(m4 - O.m4_interpolated(u)) < 1e-15
+        assert abs(mn - O.min_omega(u)) < 1e-14
+        m4x = float(rng.uniform(-0.1, 0.2))
+        w2, m42, _ = B.equilibrium_weights(u, m4=m4x)
+        if d >= 2:
+            np.testing.assert_allclose(w2, O.omega(u, m4=m4x), rtol=0, atol=1e-14)
+            assert m42 == m4x
+
+
+def test_host_weights_reject_bad_dimension():
+    with pytest.raises(B.LbmError):
+        B.equilibrium_weights([0.1] * 5)
