@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused D3Q19 stream-collide path on one MI355X.
+
+Workload: D3Q19 on the unit cube with 512 nodes per axis, full-way Dirichlet
+walls on all six faces (data from four random cosines, seed 3),
+u = (0.05, 0.1, 0.08), R = 1, tau = 1/2, third-order initialisation, fourth-order
+walls.  One step is one time step of the whole lattice (bulk kernel + wall
+kernel); `value` is the float32-storage throughput in million lattice updates
+per second with all state resident in HBM.  The float64 and float32-split
+storage modes are measured on the same workload for the precision comparison.
+
+The roofline entry is for the dominant kernel (the bulk stream-collide): its
+algorithmic bytes per launch (2 q sizeof(float) per bulk node) divided by its
+average duration from HIP events recorded around every launch on the
+library's stream during the timed region.  The CPU baseline is the float64
+oracle on a bounded sample of the same workload.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "D3Q19 MLUPS & % HBM peak, FP32 vs FP64 at fixed L2 error; adjoint/fwd ratio"
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_d3q19_512_fp32_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_13165_amd", "csrc", f)
+                  for f in ("kernels.hip", "engine.hpp", "lattice.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(bytes_per_launch: float):
+    """HBM bytes per bulk launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on other kernel sources."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    text = open(PROFILE_TRAFFIC).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_val.group(1))
+
+
+def run_mode(precision: str, steps: int, warmup: int, n: int):
+    import torch
+    from paper_2410_13165_amd import Lattice, inputs
+    w = inputs.BENCH_D3Q19
+    spec = inputs.bench_field()
+    lat = Lattice(3, (n, n, n), 0.5, dx=1.0 / (n - 1), u=w["u"], R=w["R"],
+                  bc=["fullway"] * 3, P=4, K=3, precision=precision, field=spec)
+    try:
+        info = lat.info()
+        lat.step(warmup)
+        torch.cuda.synchronize()
+        lat.profile_begin(steps)
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = lat.profile_end()
+        diag = lat.diagnostics()
+    finally:
+        lat.close()
+        torch.cuda.empty_cache()
+    seconds = t1 - t0
+    nodes = n ** 3
+    bulk_nodes = (n - 2) ** 3
+    q = info["q"]
+    esize = 8 if precision == "fp64" else 4
+    bulk_bytes = bulk_nodes * 2 * q * esize + (bulk_nodes * 16 if precision == "fp32_split" else 0)
+    bulk_s = prof["bulk_ms"] / prof["steps"] / 1e3
+    wall_s = prof["wall_ms"] / prof["steps"] / 1e3
+    return {
+        "precision": precision,
+        "mlups": nodes * steps / seconds / 1e6,
+        "ms_per_step": seconds / steps * 1e3,
+        "seconds": seconds,
+        "bytes_per_lu": info["bytes_per_lu"],
+        "hbm_frac_step": nodes * steps * info["bytes_per_lu"] / seconds / (HBM_PEAK_GBS * 1e9),
+        "bulk_ms": bulk_s * 1e3,
+        "wall_ms": wall_s * 1e3,
+        "bulk_bytes_per_launch": bulk_bytes,
+        "bulk_gbs": bulk_bytes / bulk_s / 1e9,
+        "rmse": diag["rmse"],
+        "t_final": diag["t"],
+        "nonfinite": diag["nonfinite"],
+    }
+
+
+def cpu_baseline(n_sample: int, steps: int):
+    """The FP64 oracle on a bounded sample: a cube of n_sample^3 nodes with the
+    benchmark's spacing, field and walls, for `steps` steps."""
+    from oracle import lbm_oracle as O
+    from paper_2410_13165_amd import inputs
+    from tests.pairs import oracle_problem
+    w = inputs.BENCH_D3Q19
+    spec = inputs.bench_field()
+    prob = oracle_problem(3, (n_sample,) * 3, 1.0 / (w["n"] - 1), spec, bc=["fullway"] * 3)
+    run = O.Run(prob)
+    t0 = time.perf_counter()
+    run.step(steps)
+    dt = time.perf_counter() - t0
+    return {
+        "value": n_sample ** 3 * steps / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"D3Q19 full-way, {n_sample}^3 nodes at dx=1/{w['n'] - 1}, same field, "
+                   f"{steps} steps, {dt:.1f} s, numpy float64 single thread; host has "
+                   f"{os.cpu_count()} logical CPUs"),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=512, help="nodes per axis")
+    ap.add_argument("--modes", default="fp32,fp64,fp32_split",
+                    help="storage modes; the first one gives `value`")
+    ap.add_argument("--cpu-nodes", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                          f"--gpus {args.gpus} is not supported"}), flush=True)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+
+    if args.calib_copy_gib > 0:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # give the scale between the counters and bytes
+        nbytes = int(args.calib_copy_gib * (1 << 30))
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"# calibration copy: {nbytes} bytes read and written per launch", file=sys.stderr)
+        del a, b
+        torch.cuda.empty_cache()
+
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    results = {}
+    for m in modes:
+        results[m] = run_mode(m, args.steps, args.warmup, args.n)
+        print(f"# {m}: {results[m]['mlups']:.0f} MLUPS, bulk {results[m]['bulk_gbs']:.0f} GB/s, "
+              f"rmse {results[m]['rmse']:.3e}", file=sys.stderr, flush=True)
+    head = results[modes[0]]
+
+    traffic = committed_traffic(head["bulk_bytes_per_launch"]) if modes[0] == "fp32" else None
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(head["bulk_gbs"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(head["bulk_gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": f"k_step<3,{'float' if modes[0] != 'fp64' else 'double'}> (bulk stream-collide)",
+        "bytes_per_launch": head["bulk_bytes_per_launch"],
+        "avg_launch_ms": round(head["bulk_ms"], 4),
+    }
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.cpu_nodes, args.cpu_steps)
+
+    dtype = {"fp32": "f32", "fp64": "f64", "fp32_split": "f32+f64"}[modes[0]]
+    line = {
+        "metric": METRIC,
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"D3Q19 {args.n}^3 full-way Dirichlet on all faces, 4 random cosines "
+                         "(seed 3), u=(0.05,0.1,0.08), R=1, tau=1/2, K=3, P=4, "
+                         f"{modes[0]} storage"),
+            "nodes": args.n ** 3,
+            "global_batch": 1,
+            "parallelism": "single GPU",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "hbm_frac_step": round(head["hbm_frac_step"], 4),
+        "modes": {m: {k: (float(f"{v:.6g}") if isinstance(v, float) else v)
+                      for k, v in r.items()}
+                  for m, r in results.items()},
+        "adjoint_fwd_ratio": None,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -136,6 +136,8 @@ typedef struct {
   double phi_ref;               /* LBM_FP32: phi_mean of the deviation reference      */
   int32_t bytes_per_lu;         /* algorithmic HBM bytes per lattice update of a step */
   int32_t reserved;
+  int64_t pstride;              /* elements between population planes in the state
+                                   blob of lbm_get_state (nodes first, then padding) */
 } lbm_info_t;
 
 /* Fill p with defaults: dx = 1, origin 0, u 0, R 0, g = 1/2, all axes periodic,
@@ -188,6 +190,18 @@ int lbm_get_state(const lbm_handle* h, void* dst_dev);
 /* Replace the state by a blob from lbm_get_state of a handle with the same
    parameters, taken at step `step`. */
 int lbm_set_state(lbm_handle* h, const void* src_dev, int64_t step);
+
+/* Kernel timing with HIP events recorded on the lattice's stream, for
+   benchmarks.  After lbm_profile_begin, each of the next max_steps steps
+   records events before the bulk kernel, between the bulk and the wall
+   kernel, and after the wall kernel.  lbm_profile_end synchronises the stream,
+   returns the summed durations in milliseconds of the bulk launches
+   (bulk_ms) and of the wall launches (wall_ms, 0 without Dirichlet axes) and
+   the number of profiled steps, and releases the events.  Both outputs are
+   nullable.  Errors: LBM_EINVAL (max_steps < 1 or > 2^20, profiling already
+   active / not active), LBM_EDEVICE. */
+int lbm_profile_begin(lbm_handle* h, int64_t max_steps);
+int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* steps);
 
 /* Host-only helper (no device work): the EDF weights of a DdQ(2d^2+1) lattice.
    omega_out receives 2d^2+1 values in the velocity order of Sec. 2.3, from the

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "engine.hpp"
@@ -35,6 +36,10 @@ struct lbm_handle {
   int64_t step = 0;
   bool initialised = false;
   std::string err;
+  // kernel timing (lbm_profile_begin / lbm_profile_end): 3 events per step
+  std::vector<hipEvent_t> prof_ev;
+  int64_t prof_cap = 0, prof_used = 0;
+  bool profiling = false;
 };
 
 static thread_local std::string g_create_error;
@@ -86,7 +91,9 @@ void release(lbm_handle* h) {
   }
   dev_free(h, h->partial);
   dev_free(h, h->result);
+  dev_free(h, h->kp.xdata);
   h->partial = h->result = nullptr;
+  h->kp.xdata = nullptr;
 }
 
 // Copy the analytic field into the kernel parameter block.
@@ -111,6 +118,7 @@ int setup_field(lbm_handle* h, const lbm_field* fld) {
   if (!fld->amps || !fld->kvecs) return fail(nullptr, LBM_EINVAL, "field amps/kvecs missing");
   F.kind = fld->kind == LBM_FIELD_COS_SUM ? kFieldCos : kFieldExp;
   F.nmodes = fld->n_modes;
+  const double hx = 0.5 * h->kp.dx;
   for (int j = 0; j < F.nmodes; ++j) {
     F.amp[j] = fld->amps[j];
     F.phase[j] = fld->phases ? fld->phases[j] : 0.0;
@@ -120,6 +128,13 @@ int setup_field(lbm_handle* h, const lbm_field* fld) {
       if (!std::isfinite(k)) return fail(nullptr, LBM_EINVAL, "non-finite wave vector");
       F.kvec[j][a] = k;
       ku += k * h->kp.u[a];
+      if (F.kind == kFieldCos) {
+        F.rot[j][a][0] = std::cos(hx * k);
+        F.rot[j][a][1] = std::sin(hx * k);
+      } else {
+        F.rot[j][a][0] = std::exp(-hx * k);
+        F.rot[j][a][1] = std::exp(hx * k);
+      }
     }
     F.ku[j] = ku;
   }
@@ -127,24 +142,29 @@ int setup_field(lbm_handle* h, const lbm_field* fld) {
 }
 
 void setup_faces(KParams& kp, int d) {
-  kp.nfaces = 0;
-  kp.wall_nodes = 0;
-  for (int a = 0; a < d; ++a) {
+  kp.nwfaces = 0;
+  kp.wall_rows = 0;
+  for (int a = 1; a < d; ++a) {
     if (kp.bc[a] == LBM_BC_PERIODIC) continue;
     long long cnt = 1;
-    for (int b = 0; b < d; ++b) {
+    for (int b = 1; b < d; ++b) {
       if (b == a) continue;
       const bool inner = (b < a) && kp.bc[b] != LBM_BC_PERIODIC;
       cnt *= inner ? (kp.n[b] - 2) : kp.n[b];
     }
     for (int side = 0; side < 2; ++side) {
-      kp.face_axis[kp.nfaces] = a;
-      kp.face_side[kp.nfaces] = side;
-      kp.face_count[kp.nfaces] = cnt;
-      kp.wall_nodes += cnt;
-      ++kp.nfaces;
+      kp.wface_axis[kp.nwfaces] = a;
+      kp.wface_side[kp.nwfaces] = side;
+      kp.wface_count[kp.nwfaces] = static_cast<int>(cnt);
+      kp.wall_rows += static_cast<int>(cnt);
+      ++kp.nwfaces;
     }
   }
+}
+
+size_t xdata_bytes(const lbm_handle* h) {
+  if (h->kp.bc[0] == LBM_BC_PERIODIC || h->precision != LBM_FP32_SPLIT) return 0;
+  return sizeof(double) * 2 * (2 * h->d - 1) * static_cast<size_t>(h->kp.rows);
 }
 
 int sync_result(lbm_handle* h, double* host) {
@@ -258,7 +278,15 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   }
   kp.nodes = static_cast<int>(nodes);
   kp.rows = static_cast<int>(nodes / dims[0]);
-  kp.pstride = (nodes + 63) / 64 * 64;  // 256-byte aligned population planes
+  // population planes: the nodes, then (with walls on x_1) one slot per row
+  // for the x_1-face wall data; 256-byte aligned
+  kp.xoff = static_cast<int>(nodes);
+  const int64_t plane = nodes + (p->bc[0] != LBM_BC_PERIODIC ? nodes / dims[0] : 0);
+  if (plane > std::numeric_limits<int32_t>::max()) {
+    delete h;
+    return fail(nullptr, LBM_EINVAL, "more than 2^31-1 nodes plus wall slots");
+  }
+  kp.pstride = (plane + 63) / 64 * 64;
   kp.scheme = scheme;
   kp.P = p->bc_order;
   kp.K = p->init_order;
@@ -307,7 +335,9 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   }
   h->partial = static_cast<double*>(dev_alloc(h, sizeof(double) * kRedBlocks * kNumAcc));
   h->result = static_cast<double*>(dev_alloc(h, sizeof(double) * kNumAcc));
+  if (xdata_bytes(h) > 0) kp.xdata = static_cast<double*>(dev_alloc(h, xdata_bytes(h)));
   bool ok = h->buf[0] && h->buf[1] && h->partial && h->result;
+  if (xdata_bytes(h) > 0) ok = ok && kp.xdata;
   if (h->precision == LBM_FP32_SPLIT) ok = ok && h->phib[0] && h->phib[1];
   if (!ok) {
     release(h);
@@ -375,8 +405,13 @@ int lbm_step(lbm_handle* h, int64_t n) {
   if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state (call lbm_set_initial)");
   for (int64_t i = 0; i < n; ++i) {
     const int src = h->cur, dst = 1 - h->cur;
+    hipEvent_t* ev = nullptr;
+    if (h->profiling && h->prof_used < h->prof_cap) {
+      ev = &h->prof_ev[3 * h->prof_used];
+      ++h->prof_used;
+    }
     hipError_t e = launch_step(h->kp, h->precision, h->buf[src], h->buf[dst], h->phib[src],
-                               h->phib[dst], h->step, h->stream);
+                               h->phib[dst], h->step, h->stream, ev);
     if (e != hipSuccess) return hip_fail(h, e, "step kernel");
     h->cur = dst;
     ++h->step;
@@ -426,6 +461,7 @@ int lbm_info(const lbm_handle* h, lbm_info_t* out) {
   out->phi_ref = h->kp.phi_ref;
   const int es = static_cast<int>(elem_size(h->precision));
   out->bytes_per_lu = 2 * h->q * es + (h->precision == LBM_FP32_SPLIT ? 16 : 0);
+  out->pstride = h->kp.pstride;
   return LBM_OK;
 }
 
@@ -462,6 +498,61 @@ int lbm_set_state(lbm_handle* h, const void* src_dev, int64_t step) {
   return LBM_OK;
 }
 
+namespace {
+void destroy_events(lbm_handle* h) {
+  for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+  h->prof_ev.clear();
+  h->prof_cap = h->prof_used = 0;
+  h->profiling = false;
+}
+}  // namespace
+
+int lbm_profile_begin(lbm_handle* h, int64_t max_steps) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+  if (h->profiling) return fail(h, LBM_EINVAL, "profiling already active");
+  if (max_steps < 1 || max_steps > (int64_t(1) << 20))
+    return fail(h, LBM_EINVAL, "max_steps must be in 1..2^20");
+  h->prof_ev.assign(static_cast<size_t>(3 * max_steps), nullptr);
+  for (auto& e : h->prof_ev) {
+    hipError_t rc = hipEventCreate(&e);
+    if (rc != hipSuccess) {
+      destroy_events(h);
+      return hip_fail(h, rc, "hipEventCreate");
+    }
+  }
+  h->prof_cap = max_steps;
+  h->prof_used = 0;
+  h->profiling = true;
+  return LBM_OK;
+}
+
+int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* steps) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+  if (!h->profiling) return fail(h, LBM_EINVAL, "profiling not active");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    destroy_events(h);
+    return hip_fail(h, e, "hipStreamSynchronize");
+  }
+  double b = 0.0, w = 0.0;
+  for (int64_t i = 0; i < h->prof_used; ++i) {
+    float t01 = 0.0f, t12 = 0.0f;
+    e = hipEventElapsedTime(&t01, h->prof_ev[3 * i], h->prof_ev[3 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t12, h->prof_ev[3 * i + 1], h->prof_ev[3 * i + 2]);
+    if (e != hipSuccess) {
+      destroy_events(h);
+      return hip_fail(h, e, "hipEventElapsedTime");
+    }
+    b += t01;
+    w += t12;
+  }
+  if (bulk_ms) *bulk_ms = b;
+  if (wall_ms) *wall_ms = h->kp.wall_rows > 0 ? w : 0.0;
+  if (steps) *steps = h->prof_used;
+  destroy_events(h);
+  return LBM_OK;
+}
+
 int lbm_equilibrium_weights(int d, const double* u, double g, int use_m4, double m4,
                             double* omega_out, double* m4_out, double* min_omega_out) {
   if (d < 1 || d > kMaxDim || !u || !omega_out)
@@ -483,6 +574,7 @@ const char* lbm_last_error(const lbm_handle* h) {
 int lbm_destroy(lbm_handle* h) {
   if (!h) return LBM_OK;
   (void)hipStreamSynchronize(h->stream);
+  destroy_events(h);
   release(h);
   delete h;
   return LBM_OK;

@@ -26,6 +26,10 @@ struct FieldDev {
   double phase[kMaxModes];
   double ku[kMaxModes];                 // kappa_j . u
   double kvec[kMaxModes][kMaxDim];
+  // half-cell shifts of the half-way wall points, h = dx / 2, per axis a:
+  // cos sums (cos(h kappa_ja), sin(h kappa_ja)); exp sums
+  // (exp(-h kappa_ja), exp(h kappa_ja))
+  double rot[kMaxModes][kMaxDim][2];
   double Rr, W;
   double center[kMaxDim];
 };
@@ -52,12 +56,17 @@ struct KParams {
   double shift[kMaxDim];   // 1/2 on half-way axes, else 0
   double u[kMaxDim];
   double phi_ref;          // FP32 mode: mean of phi0
-  // wall nodes, listed face by face (see k_wall)
-  int nfaces;
-  int face_axis[2 * kMaxDim];
-  int face_side[2 * kMaxDim];
-  long long face_count[2 * kMaxDim];
-  long long wall_nodes;
+  // rows on a wall of an axis >= 2, listed face by face (see k_wall)
+  int nwfaces;
+  int wface_axis[2 * kMaxDim];
+  int wface_side[2 * kMaxDim];
+  int wface_count[2 * kMaxDim];
+  int wall_rows;
+  // analytic wall data of the x_1 faces: element xoff + row of each
+  // population plane (float64 / float32 modes); split mode:
+  // xdata[(side * (2d - 1) + slot) * rows + row]
+  int xoff;
+  double* xdata;
   FieldDev field;
 };
 
@@ -70,9 +79,11 @@ LaunchShape step_shape(const KParams& p);
 
 // One time step t_n -> t_{n+1}.  Non-split modes read/write post-collision
 // populations; split mode reads/writes (phi, g) pre-collision.
+// ev (nullable): three events recorded before the bulk kernel, between the
+// bulk and the wall kernel, and after the wall kernel.
 hipError_t launch_step(const KParams& p, int mode, const void* src, void* dst,
                        const double* phi_src, double* phi_dst, long long n,
-                       hipStream_t stream);
+                       hipStream_t stream, hipEvent_t* ev = nullptr);
 
 // Initial state from the analytic field (phi0 == nullptr) or from device
 // arrays (grad0 == nullptr: fourth-order central differences).

@@ -1,11 +1,16 @@
 // gfx950 kernels of the fourth-order BGK lattice Boltzmann model.
 //
+// k_xface      analytic wall data (eq. bun1 or bun2) of the two x_1 faces for
+//              the coming step, one value per row and unknown population.
 // k_step       fused pull-streaming + BGK collision (eq. BGK-LB-Evolution) over
-//              the DdQ(2d^2+1) lattice, for every node not on a Dirichlet wall.
-// k_wall       the same update for the wall nodes, with the full-way (eq. bun1)
-//              or half-way (eq. bun2) formulas replacing the populations whose
-//              upwind node lies outside the domain.  Launched after k_step on
-//              the same stream; the two kernels write disjoint nodes.
+//              the DdQ(2d^2+1) lattice for every row that is not on a wall of
+//              an axis >= 2; its x_1-face nodes take their unknown populations
+//              from k_xface's data.
+// k_wall       the same update for the rows on a wall of an axis >= 2, with the
+//              full-way (eq. bun1) or half-way (eq. bun2) formulas replacing
+//              the populations whose upwind node lies outside the domain.
+//              The three kernels run in this order on one stream; k_step and
+//              k_wall write disjoint rows.
 // k_step_split, k_wall_split
 //              the same step on the (phi float64, g = f - omega phi float32)
 //              representation.
@@ -219,15 +224,18 @@ __device__ void field_initial(const FieldDev& F, const KParams& p, const double 
 // applied to phi*, plus (dt/2)(R_k + R_kbar), truncated at order P; the new
 // population is that minus the post-collision f*_kbar at x_f.
 
-// Value of one unknown population at a wall node x (node coordinates, d
-// components): the absolute pre-collision f_k(x, t_{n+1}).  fbar_star is the
-// post-collision f*_kbar(x, t_n), used by the half-way scheme.  Kept out of
-// line: it runs for wall nodes only and must not inflate the register budget
-// of its caller.
-__device__ __noinline__ double wall_population(const KParams& p, int k, const double* x,
-                                               double t_n, double fbar_star) {
+// Analytic wall values at one node (coordinates x) for the step
+// t_n -> t_{n+1}, for every population k with sel(k) true, into val[k]:
+// full-way: eq. (bun-1) at (x, t_{n+1}), the whole pre-collision f_k;
+// half-way: the right side of eq. (bun2) at (x - c_k dx/2, t_n), to which the
+// caller adds -f*_kbar(x, t_n).  One sincos (or exp) per mode serves every
+// population: the half-way shift -(dx/2) kappa . c_k is applied by rotating
+// with the per-axis factors of FieldDev::rot.
+template <int D, class Sel>
+__device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x)[kMaxDim],
+                                              double t_n, Sel sel, double (&val)[q_of(D)]) {
+  constexpr int Q = q_of(D);
   const FieldDev& F = p.field;
-  const int d = p.d;
   const double dt = p.dt;
   const bool full = p.scheme == kFullWay;
   const bool is_cos = F.kind == kFieldCos;
@@ -235,69 +243,174 @@ __device__ __noinline__ double wall_population(const KParams& p, int k, const do
   const double o3 = p.P >= 3 ? 1.0 : 0.0;
   const double o4 = p.P >= 4 ? 1.0 : 0.0;
   const double dt2 = dt * dt, dt3 = dt2 * dt;
-  const int kb = p.kbar[k];
-  const double wp = p.omega[k] + p.omega[kb];
-  const double wm = p.omega[k] - p.omega[kb];
-  // full-way: x_b = x at t_{n+1};  half-way: x_b = x - c_k dx / 2 at t_n
   const double t = full ? t_n + dt : t_n;
-  const double hshift = full ? 0.0 : 0.5 * p.dx;
-  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) val[k] = 0.0;
+#pragma unroll 1
   for (int j = 0; j < F.nmodes; ++j) {
-    double ph = 0.0, pc = 0.0;
-    for (int a = 0; a < d; ++a) {
-      const double xb = x[a] - hshift * p.cv[k][a];
-      ph += F.kvec[j][a] * (xb - p.u[a] * t);
-      pc += p.cv[k][a] * F.kvec[j][a];
-    }
-    const double w = -F.ku[j];
+    double ph = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ph += F.kvec[j][a] * (x[a] - p.u[a] * t);
     double C = 0.0, S = 0.0, E = 0.0;
     if (is_cos)
       sincos(ph + F.phase[j], &S, &C);
     else
       E = exp(ph);
-    if (full) {
-      const double pv = pc + w;  // kappa . (c_k - u)
-      const double pv3 = pv * pv * pv;
-      if (is_cos)
-        acc += F.amp[j] * (C + (o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3) * S);
-      else
-        acc += F.amp[j] * E * (1.0 - o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3);
-    } else {
-      const double T0 = wp;
-      const double T1 = o2 * wp * 0.5 * dt * w;
-      const double T2 = -o3 * (wp * dt2 / 8.0 * pc * pc + wm * dt2 / 4.0 * pc * w);
-      const double T3 = -o4 * (wp * (dt3 / 16.0 * pc * pc * w + dt3 / 24.0 * w * w * w) +
-                               wm * dt3 / 8.0 * pc * w * w);
-      if (is_cos)
-        acc += F.amp[j] * ((T0 - T2) * C + (T3 - T1) * S);
-      else
-        acc += F.amp[j] * (T0 + T1 + T2 + T3) * E;
-    }
+    const double amp = F.amp[j];
+    const double w = -F.ku[j];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr Vec4i c = vel_vec(D, k);
+      if (!sel(k)) return;
+      double pc = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) pc += c.v[a] * F.kvec[j][a];
+      if (full) {
+        const double pv = pc + w;  // kappa . (c_k - u)
+        const double pv3 = pv * pv * pv;
+        if (is_cos)
+          val[k] += amp * (C + (o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3) * S);
+        else
+          val[k] += amp * E * (1.0 - o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3);
+      } else {
+        constexpr int kb = opp_index(D, k);
+        const double wp = p.omega[k] + p.omega[kb];
+        const double wm = p.omega[k] - p.omega[kb];
+        const double T0 = wp;
+        const double T1 = o2 * wp * 0.5 * dt * w;
+        const double T2 = -o3 * (wp * dt2 / 8.0 * pc * pc + wm * dt2 / 4.0 * pc * w);
+        const double T3 = -o4 * (wp * (dt3 / 16.0 * pc * pc * w + dt3 / 24.0 * w * w * w) +
+                                 wm * dt3 / 8.0 * pc * w * w);
+        if (is_cos) {
+          double Ck = C, Sk = S;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (c.v[a] == 0) continue;
+            const double cr = F.rot[j][a][0];
+            const double sr = c.v[a] * F.rot[j][a][1];
+            const double nc = Ck * cr + Sk * sr;
+            Sk = Sk * cr - Ck * sr;
+            Ck = nc;
+          }
+          val[k] += amp * ((T0 - T2) * Ck + (T3 - T1) * Sk);
+        } else {
+          double Ek = E;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (c.v[a] == 1) Ek *= F.rot[j][a][0];
+            if (c.v[a] == -1) Ek *= F.rot[j][a][1];
+          }
+          val[k] += amp * (T0 + T1 + T2 + T3) * Ek;
+        }
+      }
+    });
   }
-  if (full) return p.omega[k] * (acc + p.R * t);
-  return -fbar_star + acc + wp * p.R * t_n + o2 * wp * p.R * dt;
+  static_for<0, Q>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    if (!sel(k)) return;
+    if (full) {
+      val[k] = p.omega[k] * (val[k] + p.R * t);
+    } else {
+      constexpr int kb = opp_index(D, k);
+      const double wp = p.omega[k] + p.omega[kb];
+      val[k] += wp * p.R * t_n + o2 * wp * p.R * dt;
+    }
+  });
 }
 
+// Slot of population k among those entering through the lower (c_k1 = +1) or
+// upper (c_k1 = -1) x_1 face; there are 2D - 1 of each.
+constexpr int xface_slot(int D, int k) {
+  const int cx = vel_comp(D, k, 0);
+  int slot = 0;
+  for (int m = 0; m < k; ++m)
+    if (vel_comp(D, m, 0) == cx) ++slot;
+  return slot;
+}
+
+// Wall values of every wall node of a row (any Dirichlet axis; used for the
+// rows that lie on a wall of an axis >= 2 and by the x_1 faces through
+// k_xface).  fstar_local(kb) returns the absolute post-collision f*_kb at the
+// node.
 template <int D, class A, class FStarLocal>
 __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, const RowInfo<D>& r,
                                             double t_n, double ref, FStarLocal fstar_local) {
   double x[kMaxDim] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int a = 0; a < D; ++a) x[a] = p.origin[a] + (r.i[a] + p.shift[a]) * p.dx;
+  bool out[q_of(D)];
   static_for<0, q_of(D)>([&](auto K) {
     constexpr int k = decltype(K)::value;
-    if (!outside<D, k>(r)) return;
-    constexpr int kb = opp_index(D, k);
-    const double fbs = (p.scheme == kHalfWay) ? fstar_local(kb) : 0.0;
-    const double val = wall_population(p, k, x, t_n, fbs);
-    f[k] = static_cast<A>(val - p.omega[k] * ref);
+    out[k] = outside<D, k>(r);
+  });
+  double val[q_of(D)];
+  wall_analytic<D>(p, x, t_n, [&](int k) { return out[k]; }, val);
+  const bool half = p.scheme == kHalfWay;
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    if (!out[k]) return;
+    double v = val[k];
+    if (half) v -= fstar_local(opp_index(D, k));
+    f[k] = static_cast<A>(v - p.omega[k] * ref);
+  });
+}
+
+// Analytic wall data of the x_1 faces for the step t_n -> t_{n+1}: one
+// thread per (face, row).  A population with c_k1 = +1 (-1) is unknown on the
+// lower (upper) x_1 face only, so its value for row `row` is kept in its own
+// population plane of the source buffer, at element p.xoff + row past the
+// nodes; the bulk kernel then reads it with the same base address as its
+// pulls.  Values are stored in the storage type T:
+//   full-way  f_k - omega_k ref,
+//   half-way  B_k - (omega_k + omega_kbar) ref  (the bulk kernel subtracts the
+//             stored post-collision kbar value of the node),
+// with ref = phi_ref + R t_{n+1} in float32 mode and 0 otherwise.  The split
+// mode keeps float64 values in p.xdata[(side * (2D-1) + slot) * rows + row].
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_xface(T* __restrict__ buf, const KParams p, const double t_n, const int mode) {
+  constexpr int S = 2 * D - 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * p.rows) return;
+  const int side = idx >= p.rows ? 1 : 0;
+  const int row = idx - side * p.rows;
+  double x[kMaxDim] = {0.0, 0.0, 0.0, 0.0};
+  x[0] = p.origin[0] + ((side ? p.n[0] - 1 : 0) + p.shift[0]) * p.dx;
+  int rr = row;
+#pragma unroll
+  for (int a = 1; a < D; ++a) {
+    const int ia = rr % p.n[a];
+    rr /= p.n[a];
+    x[a] = p.origin[a] + (ia + p.shift[a]) * p.dx;
+  }
+  const double ref = (mode == kFP32) ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
+  const bool half = p.scheme == kHalfWay;
+  const long long ps = p.pstride;
+  const int want = side ? -1 : 1;
+  double val[q_of(D)];
+  wall_analytic<D>(p, x, t_n, [&](int k) { return p.cv[k][0] == want; }, val);
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int cx = vel_comp(D, k, 0);
+    if constexpr (cx == 0) {
+      return;
+    } else {
+      if (cx != want) return;
+      if (mode == kSplit) {
+        p.xdata[((long long)side * S + xface_slot(D, k)) * p.rows + row] = val[k];
+      } else {
+        constexpr int kb = opp_index(D, k);
+        const double wref = (half ? p.omega[k] + p.omega[kb] : p.omega[k]) * ref;
+        buf[k * ps + p.xoff + row] = static_cast<T>(val[k] - wref);
+      }
+    }
   });
 }
 
 // ------------------------------------------------------------ step kernels --
 
 // Collision of the pulled pre-collision populations and store of the
-// post-collision ones.  float64: f*_k = (1-s) f_k + s omega_k phi + dt omega_k R.
+// post-collision ones (non-temporal stores: nothing rereads them this step).  float64: f*_k = (1-s) f_k + s omega_k phi + dt omega_k R.
 // float32 stores deviations from the uniform exact state omega_k (phi_ref + R t),
 // which is a fixed point of stream + collide, so the deviations follow the same
 // update without the source term; phi is summed with TwoSum compensation.
@@ -316,7 +429,8 @@ __device__ __forceinline__ void collide_store(T (&f)[q_of(D)], T* __restrict__ d
     const float phi = sum + comp;
     const float oms = 1.0f - p.s_f;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) dst[k * ps + node] = fmaf(p.s_f * p.omega_f[k], phi, oms * f[k]);
+    for (int k = 0; k < Q; ++k)
+      __builtin_nontemporal_store(fmaf(p.s_f * p.omega_f[k], phi, oms * f[k]), dst + k * ps + node);
   } else {
     double phi = 0.0;
 #pragma unroll
@@ -325,12 +439,17 @@ __device__ __forceinline__ void collide_store(T (&f)[q_of(D)], T* __restrict__ d
     const double dtR = p.dt * p.R;
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-      dst[k * ps + node] = fma(p.s * p.omega[k], phi, fma(oms, f[k], dtR * p.omega[k]));
+      __builtin_nontemporal_store(fma(p.s * p.omega[k], phi, fma(oms, f[k], dtR * p.omega[k])),
+                                  dst + k * ps + node);
   }
 }
 
-// Bulk nodes: post-collision populations stored (float64, or float32
-// deviations).  Nodes on a Dirichlet wall are left to k_wall.
+// Bulk rows: post-collision populations stored (float64, or float32
+// deviations from omega_k (phi_ref + R t_{n+1})).  Rows on a wall of an axis
+// >= 2 are left to k_wall.  On the x_1 faces the unknown populations are read
+// from k_xface's data instead of the upwind node (an index select on the same
+// base address, so the common path keeps its registers); the half-way scheme
+// then subtracts the node's own post-collision kbar value.
 template <int D, class T>
 __global__ void __launch_bounds__(256)
     k_step(const T* __restrict__ src, T* __restrict__ dst, const KParams p) {
@@ -341,15 +460,30 @@ __global__ void __launch_bounds__(256)
   row_setup<D>(p, row, r);
   if (r.rowwall) return;
   const long long ps = p.pstride;
+  const bool half = p.scheme == kHalfWay;
   for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
     col_setup<D>(p, x, r);
-    if (r.lo[0] || r.hi[0]) continue;
     const int node = r.rowbase + x;
+    const bool xwall = r.lo[0] || r.hi[0];
     T f[Q];
     static_for<0, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      f[k] = src[k * ps + node + pull_offset<D, k>(r)];
+      constexpr int cx = vel_comp(D, k, 0);
+      int idx = node + pull_offset<D, k>(r);
+      if constexpr (cx != 0) {
+        if ((cx == 1) ? r.lo[0] : r.hi[0]) idx = p.xoff + row;
+      }
+      f[k] = src[k * ps + idx];
     });
+    if (xwall && half) {
+      static_for<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr int cx = vel_comp(D, k, 0);
+        if constexpr (cx != 0) {
+          if ((cx == 1) ? r.lo[0] : r.hi[0]) f[k] -= src[opp_index(D, k) * ps + node];
+        }
+      });
+    }
     collide_store<D, T>(f, dst, ps, node, p);
   }
 }
@@ -372,6 +506,14 @@ __device__ __forceinline__ void split_pull(double (&f)[q_of(D)], const float* __
 }
 
 template <int D>
+__device__ __forceinline__ double split_fstar(const float* __restrict__ gsrc,
+                                              const double* __restrict__ phisrc, long long ps,
+                                              int node, int kb, const KParams& p) {
+  return fma(p.omega[kb], phisrc[node],
+             fma(1.0 - p.s, static_cast<double>(gsrc[kb * ps + node]), p.dt * p.R * p.omega[kb]));
+}
+
+template <int D>
 __device__ __forceinline__ void split_store(const double (&f)[q_of(D)], float* __restrict__ gdst,
                                             double* __restrict__ phidst, long long ps, int node,
                                             const KParams& p) {
@@ -379,9 +521,10 @@ __device__ __forceinline__ void split_store(const double (&f)[q_of(D)], float* _
   double phi = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) phi += f[k];
-  phidst[node] = phi;
+  __builtin_nontemporal_store(phi, phidst + node);
 #pragma unroll
-  for (int k = 0; k < Q; ++k) gdst[k * ps + node] = static_cast<float>(f[k] - p.omega[k] * phi);
+  for (int k = 0; k < Q; ++k)
+    __builtin_nontemporal_store(static_cast<float>(f[k] - p.omega[k] * phi), gdst + k * ps + node);
 }
 
 template <int D>
@@ -389,62 +532,65 @@ __global__ void __launch_bounds__(256)
     k_step_split(const float* __restrict__ gsrc, float* __restrict__ gdst,
                  const double* __restrict__ phisrc, double* __restrict__ phidst, const KParams p) {
   constexpr int Q = q_of(D);
+  constexpr int S = 2 * D - 1;
   const int row = blockIdx.x * blockDim.y + threadIdx.y;
   if (row >= p.rows) return;
   RowInfo<D> r;
   row_setup<D>(p, row, r);
   if (r.rowwall) return;
   const long long ps = p.pstride;
+  const bool half = p.scheme == kHalfWay;
   for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
     col_setup<D>(p, x, r);
-    if (r.lo[0] || r.hi[0]) continue;
     const int node = r.rowbase + x;
     double f[Q];
     split_pull<D>(f, gsrc, phisrc, ps, node, r, p);
+    if (r.lo[0] || r.hi[0]) {
+      const double* W = p.xdata + (r.hi[0] ? S * p.rows : 0) + row;
+      static_for<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr int cx = vel_comp(D, k, 0);
+        if constexpr (cx != 0) {
+          if ((cx == 1) ? r.lo[0] : r.hi[0]) {
+            double v = W[(long long)xface_slot(D, k) * p.rows];
+            if (half) v -= split_fstar<D>(gsrc, phisrc, ps, node, opp_index(D, k), p);
+            f[k] = v;
+          }
+        }
+      });
+    }
     split_store<D>(f, gdst, phidst, ps, node, p);
   }
 }
 
-// Wall nodes.  Face (a, side) lists the nodes with i_a at that side whose
-// indices on the Dirichlet axes b < a are interior, so every wall node is
-// visited exactly once.
+// Rows on a wall of an axis >= 2.  Face (a, side), a >= 2, lists the rows
+// with i_a at that side whose indices on the Dirichlet axes 2 <= b < a are
+// interior, so every wall row is visited once; threads run along x_1 as in the
+// bulk kernels, so loads and stores stay coalesced.
 template <int D>
-__device__ __forceinline__ bool wall_node(const KParams& p, long long idx, RowInfo<D>& r) {
+__device__ __forceinline__ int wall_row(const KParams& p, int idx) {
   int f = 0;
-  while (f < p.nfaces && idx >= p.face_count[f]) {
-    idx -= p.face_count[f];
+  while (f < p.nwfaces - 1 && idx >= p.wface_count[f]) {
+    idx -= p.wface_count[f];
     ++f;
   }
-  if (f >= p.nfaces) return false;
-  const int a0 = p.face_axis[f];
-  long long l = idx;
+  const int a0 = p.wface_axis[f];
+  int l = idx, row = 0, rstride = 1;
 #pragma unroll
-  for (int b = 0; b < D; ++b) {
+  for (int b = 1; b < D; ++b) {
+    int ib;
     if (b == a0) {
-      r.i[b] = p.face_side[f] ? p.n[b] - 1 : 0;
-      continue;
+      ib = p.wface_side[f] ? p.n[b] - 1 : 0;
+    } else {
+      const bool inner = (b < a0) && p.bc[b] != 0;
+      const int nb = inner ? p.n[b] - 2 : p.n[b];
+      ib = l % nb + (inner ? 1 : 0);
+      l /= nb;
     }
-    const bool inner = (b < a0) && p.bc[b] != 0;
-    const int nb = inner ? p.n[b] - 2 : p.n[b];
-    r.i[b] = static_cast<int>(l % nb) + (inner ? 1 : 0);
-    l /= nb;
+    row += ib * rstride;
+    rstride *= p.n[b];
   }
-  int node = 0;
-  r.rowwall = false;
-#pragma unroll
-  for (int b = 0; b < D; ++b) {
-    const int n = p.n[b];
-    const int st = p.stride[b];
-    const int ib = r.i[b];
-    node += ib * st;
-    r.dm[b] = (ib == 0) ? (n - 1) * st : -st;
-    r.dp[b] = (ib == n - 1) ? -(n - 1) * st : st;
-    const bool wall = p.bc[b] != 0;
-    r.lo[b] = wall && ib == 0;
-    r.hi[b] = wall && ib == n - 1;
-  }
-  r.rowbase = node;  // node index of this wall node
-  return true;
+  return row;
 }
 
 template <int D, class T>
@@ -452,14 +598,17 @@ __global__ void __launch_bounds__(256)
     k_wall(const T* __restrict__ src, T* __restrict__ dst, const KParams p, const double t_n) {
   constexpr int Q = q_of(D);
   constexpr bool kF32 = std::is_same<T, float>::value;
+  const int widx = blockIdx.x * blockDim.y + threadIdx.y;
+  if (widx >= p.wall_rows) return;
+  const int row = wall_row<D>(p, widx);
+  RowInfo<D> r;
+  row_setup<D>(p, row, r);
   const long long ps = p.pstride;
   // reference of the float32 deviations at t_{n+1}
   const double ref = kF32 ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < p.wall_nodes;
-       idx += (long long)gridDim.x * blockDim.x) {
-    RowInfo<D> r;
-    if (!wall_node<D>(p, idx, r)) continue;
-    const int node = r.rowbase;
+  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+    col_setup<D>(p, x, r);
+    const int node = r.rowbase + x;
     T f[Q];
     static_for<0, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
@@ -478,19 +627,19 @@ __global__ void __launch_bounds__(256)
                  const double* __restrict__ phisrc, double* __restrict__ phidst, const KParams p,
                  const double t_n) {
   constexpr int Q = q_of(D);
+  const int widx = blockIdx.x * blockDim.y + threadIdx.y;
+  if (widx >= p.wall_rows) return;
+  const int row = wall_row<D>(p, widx);
+  RowInfo<D> r;
+  row_setup<D>(p, row, r);
   const long long ps = p.pstride;
-  const double oms = 1.0 - p.s;
-  const double dtR = p.dt * p.R;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < p.wall_nodes;
-       idx += (long long)gridDim.x * blockDim.x) {
-    RowInfo<D> r;
-    if (!wall_node<D>(p, idx, r)) continue;
-    const int node = r.rowbase;
+  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+    col_setup<D>(p, x, r);
+    const int node = r.rowbase + x;
     double f[Q];
     split_pull<D>(f, gsrc, phisrc, ps, node, r, p);
     wall_values<D, double>(f, p, r, t_n, 0.0, [&](int kb) {
-      return fma(p.omega[kb], phisrc[node],
-                 fma(oms, static_cast<double>(gsrc[kb * ps + node]), dtR * p.omega[kb]));
+      return split_fstar<D>(gsrc, phisrc, ps, node, kb, p);
     });
     split_store<D>(f, gdst, phidst, ps, node, p);
   }
@@ -732,42 +881,59 @@ static unsigned grid_for(long long nodes, int threads) {
 template <int D>
 static hipError_t step_d(const KParams& p, int mode, const void* src, void* dst,
                          const double* phi_src, double* phi_dst, long long n,
-                         hipStream_t stream) {
+                         hipStream_t stream, hipEvent_t* ev) {
   const LaunchShape s = step_shape(p);
   const dim3 block(s.tx, s.ty), grid(s.blocks);
+  const dim3 wgrid(static_cast<unsigned>((p.wall_rows + s.ty - 1) / s.ty));
   const double t_n = static_cast<double>(n) * p.dt;
-  const dim3 wblock(256), wgrid(grid_for(p.wall_nodes, 256));
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], stream);
+  };
+  if (p.bc[0] != 0) {
+    const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
+    if (mode == kFP64)
+      hipLaunchKernelGGL((k_xface<D, double>), dim3(xb), dim3(256), 0, stream,
+                         static_cast<double*>(const_cast<void*>(src)), p, t_n, mode);
+    else
+      hipLaunchKernelGGL((k_xface<D, float>), dim3(xb), dim3(256), 0, stream,
+                         static_cast<float*>(const_cast<void*>(src)), p, t_n, mode);
+  }
+  mark(0);
   if (mode == kFP64) {
     auto* a = static_cast<const double*>(src);
     auto* b = static_cast<double*>(dst);
     hipLaunchKernelGGL((k_step<D, double>), grid, block, 0, stream, a, b, p);
-    if (p.wall_nodes > 0)
-      hipLaunchKernelGGL((k_wall<D, double>), wgrid, wblock, 0, stream, a, b, p, t_n);
+    mark(1);
+    if (p.wall_rows > 0)
+      hipLaunchKernelGGL((k_wall<D, double>), wgrid, block, 0, stream, a, b, p, t_n);
   } else if (mode == kFP32) {
     auto* a = static_cast<const float*>(src);
     auto* b = static_cast<float*>(dst);
     hipLaunchKernelGGL((k_step<D, float>), grid, block, 0, stream, a, b, p);
-    if (p.wall_nodes > 0)
-      hipLaunchKernelGGL((k_wall<D, float>), wgrid, wblock, 0, stream, a, b, p, t_n);
+    mark(1);
+    if (p.wall_rows > 0)
+      hipLaunchKernelGGL((k_wall<D, float>), wgrid, block, 0, stream, a, b, p, t_n);
   } else {
     auto* a = static_cast<const float*>(src);
     auto* b = static_cast<float*>(dst);
     hipLaunchKernelGGL((k_step_split<D>), grid, block, 0, stream, a, b, phi_src, phi_dst, p);
-    if (p.wall_nodes > 0)
-      hipLaunchKernelGGL((k_wall_split<D>), wgrid, wblock, 0, stream, a, b, phi_src, phi_dst, p,
+    mark(1);
+    if (p.wall_rows > 0)
+      hipLaunchKernelGGL((k_wall_split<D>), wgrid, block, 0, stream, a, b, phi_src, phi_dst, p,
                          t_n);
   }
+  mark(2);
   return hipGetLastError();
 }
 
 hipError_t launch_step(const KParams& p, int mode, const void* src, void* dst,
                        const double* phi_src, double* phi_dst, long long n,
-                       hipStream_t stream) {
+                       hipStream_t stream, hipEvent_t* ev) {
   switch (p.d) {
-    case 1: return step_d<1>(p, mode, src, dst, phi_src, phi_dst, n, stream);
-    case 2: return step_d<2>(p, mode, src, dst, phi_src, phi_dst, n, stream);
-    case 3: return step_d<3>(p, mode, src, dst, phi_src, phi_dst, n, stream);
-    case 4: return step_d<4>(p, mode, src, dst, phi_src, phi_dst, n, stream);
+    case 1: return step_d<1>(p, mode, src, dst, phi_src, phi_dst, n, stream, ev);
+    case 2: return step_d<2>(p, mode, src, dst, phi_src, phi_dst, n, stream, ev);
+    case 3: return step_d<3>(p, mode, src, dst, phi_src, phi_dst, n, stream, ev);
+    case 4: return step_d<4>(p, mode, src, dst, phi_src, phi_dst, n, stream, ev);
     default: return hipErrorInvalidValue;
   }
 }

@@ -59,7 +59,7 @@ class LbmInfo(C.Structure):
         ("dims", C.c_int64 * MAX_DIM), ("nodes", C.c_int64), ("step", C.c_int64),
         ("omega", C.c_double * MAX_Q), ("m4", C.c_double), ("min_omega", C.c_double),
         ("s", C.c_double), ("dt", C.c_double), ("phi_ref", C.c_double),
-        ("bytes_per_lu", C.c_int32), ("reserved", C.c_int32),
+        ("bytes_per_lu", C.c_int32), ("reserved", C.c_int32), ("pstride", C.c_int64),
     ]
 
 
@@ -78,6 +78,9 @@ SIGNATURES = {
     "lbm_equilibrium_weights": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.c_double, C.c_int,
                                            C.c_double, C.POINTER(C.c_double),
                                            C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lbm_profile_begin": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_int64)]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_destroy": (C.c_int, [C.c_void_p]),
 }
@@ -289,7 +292,17 @@ class Lattice:
             "dims": tuple(inf.dims[: inf.d]), "nodes": inf.nodes, "step": inf.step,
             "omega": np.array(inf.omega[: inf.q]), "m4": inf.m4, "min_omega": inf.min_omega,
             "s": inf.s, "dt": inf.dt, "phi_ref": inf.phi_ref, "bytes_per_lu": inf.bytes_per_lu,
+            "pstride": inf.pstride,
         }
+
+    def profile_begin(self, max_steps: int):
+        self._check(self.lib.lbm_profile_begin(self._h, int(max_steps)))
+        return self
+
+    def profile_end(self) -> dict:
+        b, w, n = C.c_double(), C.c_double(), C.c_int64()
+        self._check(self.lib.lbm_profile_end(self._h, C.byref(b), C.byref(w), C.byref(n)))
+        return {"bulk_ms": b.value, "wall_ms": w.value, "steps": n.value}
 
     def state_bytes(self) -> int:
         return int(self.lib.lbm_state_bytes(self._h))

@@ -63,7 +63,7 @@ def gpu_populations(lat, info=None) -> np.ndarray:
     q, nodes = info["q"], info["nodes"]
     blob = lat.get_state()
     torch.cuda.synchronize()
-    pstride = (nodes + 63) // 64 * 64
+    pstride = info["pstride"]
     dims_rev = tuple(reversed(lat.dims))
     omega = info["omega"]
     if lat.precision == "fp64":

@@ -58,7 +58,7 @@ int main(void) {
   P(lbm_field, Rr); P(lbm_field, W); P(lbm_field, center);
   P(lbm_info_t, dims); P(lbm_info_t, nodes); P(lbm_info_t, step); P(lbm_info_t, omega);
   P(lbm_info_t, m4); P(lbm_info_t, min_omega); P(lbm_info_t, s); P(lbm_info_t, dt);
-  P(lbm_info_t, phi_ref); P(lbm_info_t, bytes_per_lu);
+  P(lbm_info_t, phi_ref); P(lbm_info_t, bytes_per_lu); P(lbm_info_t, pstride);
   return 0;
 }
 """
