@@ -10,7 +10,8 @@ per second with all state resident in HBM.  The float64 and float32-split
 storage modes are measured on the same workload for the precision comparison.
 
 The roofline entry is for the dominant kernel (the bulk stream-collide): its
-algorithmic bytes per launch (2 q sizeof(float) per bulk node) divided by its
+algorithmic bytes per launch (2 q sizeof(float) per node of the (n-2)^2 rows
+off the y/z walls) divided by its
 average duration from HIP events recorded around every launch on the
 library's stream during the timed region.  The CPU baseline is the float64
 oracle on a bounded sample of the same workload.
@@ -82,7 +83,9 @@ def run_mode(precision: str, steps: int, warmup: int, n: int):
         torch.cuda.empty_cache()
     seconds = t1 - t0
     nodes = n ** 3
-    bulk_nodes = (n - 2) ** 3
+    # the bulk kernel updates every row that is not on a y/z wall, x_1-face
+    # nodes included: (n - 2)^2 rows of n nodes
+    bulk_nodes = (n - 2) ** 2 * n
     q = info["q"]
     esize = 8 if precision == "fp64" else 4
     bulk_bytes = bulk_nodes * 2 * q * esize + (bulk_nodes * 16 if precision == "fp32_split" else 0)
