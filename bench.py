@@ -108,6 +108,58 @@ def run_mode(precision: str, steps: int, warmup: int, n: int):
     }
 
 
+def run_adjoint(precision: str = "fp32", n=None, steps=None):
+    """Forward with checkpoint tape, then the adjoint gradient (dL/dphi0 and
+    dL/dtau) on the gradient workload; returns the backward / forward time ratio."""
+    import numpy as np
+    import torch
+    from paper_2410_13165_amd import Lattice, inputs
+    w = inputs.ADJOINT_D3Q19
+    n = n or w["n"]
+    steps = steps or w["steps"]
+    dx = 1.0 / n
+    phi0 = torch.from_numpy(inputs.gaussian_random_field(n, 3, w["seed_init"], w["corr"]).ravel())
+    tgt = torch.from_numpy(inputs.gaussian_random_field(n, 3, w["seed_target"], w["corr"]))
+    lat = Lattice(3, (n, n, n), 0.5, dx=dx, u=w["u"], precision=precision)
+    try:
+        lat.set_initial(phi0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.tape_begin(w["every"])
+        lat.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        phiN = lat.phi()
+        seed = (phiN - tgt.to(phiN.device)) * dx ** 3
+        loss = 0.5 * float((phiN - tgt.to(phiN.device)).pow(2).sum()) * dx ** 3
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g = lat.tape_gradient(seed, want_phi0=True, want_tau=True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        g2 = lat.tape_gradient(seed, want_phi0=True, want_tau=False)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        gnorm = float(g["phi0"].norm())
+        lat.tape_end()
+    finally:
+        lat.close()
+        torch.cuda.empty_cache()
+    fwd = t1 - t0
+    return {
+        "workload": (f"D3Q19 {n}^3 periodic, {precision}, {steps} steps, checkpoints every "
+                     f"{w['every']}, Gaussian random fields (corr {w['corr']})"),
+        "forward_s": fwd,
+        "backward_s": t3 - t2,
+        "ratio": (t3 - t2) / fwd,
+        "backward_phi0_only_s": t4 - t3,
+        "ratio_phi0_only": (t4 - t3) / fwd,
+        "loss": loss,
+        "dL_dtau": g["tau"],
+        "grad_phi0_norm": gnorm,
+    }
+
+
 def cpu_baseline(n_sample: int, steps: int):
     """The FP64 oracle on a bounded sample: a cube of n_sample^3 nodes with the
     benchmark's spacing, field and walls, for `steps` steps."""
@@ -143,6 +195,7 @@ def main(argv=None):
     ap.add_argument("--cpu-nodes", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args(argv)
@@ -177,6 +230,11 @@ def main(argv=None):
         print(f"# {m}: {results[m]['mlups']:.0f} MLUPS, bulk {results[m]['bulk_gbs']:.0f} GB/s, "
               f"rmse {results[m]['rmse']:.3e}", file=sys.stderr, flush=True)
     head = results[modes[0]]
+    adj = None
+    if not args.no_adjoint:
+        adj = run_adjoint("fp32")
+        print(f"# adjoint: forward {adj['forward_s']:.3f} s, backward {adj['backward_s']:.3f} s, "
+              f"ratio {adj['ratio']:.3f}", file=sys.stderr, flush=True)
 
     traffic = committed_traffic(head["bulk_bytes_per_launch"]) if modes[0] == "fp32" else None
     roofline = {
@@ -222,7 +280,9 @@ def main(argv=None):
         "modes": {m: {k: (float(f"{v:.6g}") if isinstance(v, float) else v)
                       for k, v in r.items()}
                   for m, r in results.items()},
-        "adjoint_fwd_ratio": None,
+        "adjoint_fwd_ratio": round(adj["ratio"], 4) if adj else None,
+        "adjoint": ({k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in adj.items()}
+                    if adj else None),
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -203,6 +203,36 @@ int lbm_set_state(lbm_handle* h, const void* src_dev, int64_t step);
 int lbm_profile_begin(lbm_handle* h, int64_t max_steps);
 int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* steps);
 
+/* Gradients of a final-time misfit L(phi^N) by the adjoint (transposed)
+   stream-collide (see adjoint.hip): the step is linear in the populations,
+   f^{n+1} = P_in S (C f^n + b) + wall values, so dL/df^n = C^T S^T P_in^T dL/df^{n+1}
+   plus, on half-way walls, the local reflected coupling; populations that
+   leave the domain carry no adjoint (their replacements come from the wall
+   data).
+   lbm_tape_begin(h, every) checkpoints the current state (at step n0) and then
+   every `every` steps taken by lbm_step (device copies through the allocator).
+   lbm_tape_gradient(h, dl_dphi, ...) takes dL/dphi^N (device float64, one value
+   per node, N = current step) and returns, all nullable:
+     dl_dphi0  (device float64, N nodes)  dL/dphi0, through the transpose of the
+               initialisation; with finite-difference gradients (lbm_set_initial
+               without grad) their transpose is folded in;
+     dl_dgrad0 (device float64, d planes) dL/d(grad phi0) for initial states built
+               from an explicit or analytic gradient (tau dt sum_k omega_k (u - c_k) lambda_k);
+     dl_dtau   (host) dL/dtau, the sum over the steps of
+               <dL/dg^n, (omega 1^T - I) f^n> d s/d tau plus the initialisation's
+               tau dependence.  It replays each segment from its checkpoint
+               (segment buffers of `every` states), so memory is
+               (n_ckpt + every) states; without it no replay is needed.
+   The phi0 outputs need a tape that starts at step 0 right after lbm_create
+   with a field or lbm_set_initial.  The handle's state is left unchanged.
+   Errors: LBM_EINVAL (no tape, NULL dl_dphi, phi0 outputs without an initial
+   tape), LBM_EUNSUPPORTED (dL/dtau at s = 1 with post-collision storage),
+   LBM_ENOMEM, LBM_EDEVICE.  lbm_tape_end frees the checkpoints. */
+int lbm_tape_begin(lbm_handle* h, int64_t every);
+int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0_dev,
+                      double* dl_dgrad0_dev, double* dl_dtau_host);
+int lbm_tape_end(lbm_handle* h);
+
 /* Host-only helper (no device work): the EDF weights of a DdQ(2d^2+1) lattice.
    omega_out receives 2d^2+1 values in the velocity order of Sec. 2.3, from the
    closed form eq. (omega_k-2) with one m4 for every pair (Remark 5); m4 is the

@@ -1,0 +1,392 @@
+// Adjoint (transposed) kernels of the lattice Boltzmann step, for gradients of
+// a final-time misfit L(phi^N).
+//
+// The stored forward state is g^n = C f^n + b (post-collision; C = (1-s) I +
+// s omega 1^T, b = dt omega R) or, in the split mode, the pre-collision f^n.
+// One forward step is f^{n+1} = P_in S g^n + (wall values), S the pull
+// streaming; on half-way walls the wall value also holds -g^n_kbar(x_f).
+// With lambda^n = dL/df^n and nu^n = dL/dg^n:
+//   nu^n     = S^T P_in^T lambda^{n+1}  (minus lambda^{n+1}_k(x_f) in the kbar
+//                                        component at half-way wall nodes)
+//   lambda^n = C^T nu^n,   (C^T v)_k = (1-s) v_k + s sum_j omega_j v_j.
+// S^T is a pull from x + c_k; populations that leave the domain contribute 0.
+// The seed is lambda^N = dL/dphi^N for every k (phi = sum_k f_k).
+// dL/ds = sum_{n<N} <nu^n, (omega 1^T - I) f^n>, with f^n recovered from the
+// stored g^n.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "engine.hpp"
+
+namespace lbm {
+
+namespace {
+
+template <int I, int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    sfor<I + 1, N>(f);
+  }
+}
+
+struct CV4 {
+  int v[4];
+};
+
+constexpr CV4 cvec(int D, int k) {
+  CV4 r{{0, 0, 0, 0}};
+  for (int a = 0; a < D; ++a) r.v[a] = vel_comp(D, k, a);
+  return r;
+}
+
+template <int D>
+struct Nb {
+  int i[D];
+  int dm[D];  // offset of the node at i_a - 1 (wrapped)
+  int dp[D];  // offset of the node at i_a + 1 (wrapped)
+  bool lo[D];
+  bool hi[D];
+  int rowbase;
+};
+
+template <int D>
+__device__ __forceinline__ void nb_row(const KParams& p, int row, Nb<D>& r) {
+  int rr = row;
+#pragma unroll
+  for (int a = 1; a < D; ++a) {
+    const int n = p.n[a];
+    const int ia = rr % n;
+    rr /= n;
+    const int st = p.stride[a];
+    r.i[a] = ia;
+    r.dm[a] = (ia == 0) ? (n - 1) * st : -st;
+    r.dp[a] = (ia == n - 1) ? -(n - 1) * st : st;
+    const bool wall = p.bc[a] != 0;
+    r.lo[a] = wall && ia == 0;
+    r.hi[a] = wall && ia == n - 1;
+  }
+  r.rowbase = row * p.n[0];
+}
+
+template <int D>
+__device__ __forceinline__ void nb_col(const KParams& p, int x, Nb<D>& r) {
+  const int n0 = p.n[0];
+  r.i[0] = x;
+  r.dm[0] = (x == 0) ? n0 - 1 : -1;
+  r.dp[0] = (x == n0 - 1) ? -(n0 - 1) : 1;
+  const bool wall = p.bc[0] != 0;
+  r.lo[0] = wall && x == 0;
+  r.hi[0] = wall && x == n0 - 1;
+}
+
+// node offset of x + c_k (wrapped) and whether x + c_k leaves the domain
+template <int D, int k>
+__device__ __forceinline__ int push_offset(const Nb<D>& r) {
+  constexpr CV4 c = cvec(D, k);
+  int off = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (c.v[a] == 1) off += r.dp[a];
+    if (c.v[a] == -1) off += r.dm[a];
+  }
+  return off;
+}
+
+template <int D, int k>
+__device__ __forceinline__ bool leaves(const Nb<D>& r) {
+  constexpr CV4 c = cvec(D, k);
+  bool o = false;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (c.v[a] == 1) o = o || r.hi[a];
+    if (c.v[a] == -1) o = o || r.lo[a];
+  }
+  return o;
+}
+
+// Block sum of v; thread 0 stores it to *out, or adds it when accumulate.
+__device__ __forceinline__ void block_sum(double v, double* sh, double* out,
+                                          bool accumulate = false) {
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int nt = blockDim.x * blockDim.y;
+  sh[tid] = v;
+  __syncthreads();
+  for (int half = 128; half > 0; half >>= 1) {
+    if (tid < half && tid + half < nt) sh[tid] += sh[tid + half];
+    __syncthreads();
+  }
+  if (tid == 0) *out = accumulate ? *out + sh[0] : sh[0];
+}
+
+}  // namespace
+
+// One adjoint step lambda^{n+1} -> lambda^n over every row.  `g` is the
+// forward state at step n (post-collision g^n, or the split (phi, g) pair);
+// when it is given, the block's share of <nu^n, (omega 1^T - I) f^n> is added
+// to partial[block] (for dL/ds, without the 1/(1-s) factor of the
+// post-collision modes, which the host applies); every block adds its own
+// steps in order, so the final sum is deterministic.
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_adjoint(const T* __restrict__ lsrc, T* __restrict__ ldst, const T* __restrict__ g,
+              const double* __restrict__ gphi, const KParams p, const int mode,
+              double* __restrict__ partial) {
+  constexpr int Q = q_of(D);
+  __shared__ double sh[256];
+  const int row = blockIdx.x * blockDim.y + threadIdx.y;
+  double acc = 0.0;
+  if (row < p.rows) {
+    Nb<D> r;
+    nb_row<D>(p, row, r);
+    const long long ps = p.pstride;
+    const bool half = p.scheme == kHalfWay;
+    for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+      nb_col<D>(p, x, r);
+      const int node = r.rowbase + x;
+      T mu[Q];
+      sfor<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        mu[k] = lsrc[k * ps + node + push_offset<D, k>(r)];
+      });
+      // populations that leave the domain: zero, or on half-way walls the
+      // reflected coupling -lambda_kbar(x) of the wall formula
+      sfor<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if (leaves<D, k>(r)) {
+          constexpr int kb = opp_index(D, k);
+          mu[k] = half ? -lsrc[kb * ps + node] : T(0);
+        }
+      });
+      double m = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) m += p.omega[k] * static_cast<double>(mu[k]);
+      const T ms = static_cast<T>(p.s * m);
+      const T oms = static_cast<T>(1.0 - p.s);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(oms * mu[k] + ms, ldst + k * ps + node);
+      if (g) {
+        // (omega 1^T - I) f^n at this node
+        double z[Q];
+        if (mode == kSplit) {
+#pragma unroll
+          for (int k = 0; k < Q; ++k) z[k] = -static_cast<double>(g[k * ps + node]);
+        } else {
+          // omega_k phi + dt omega_k R - g_k with phi = sum_j g_j - dt R, which is
+          // omega_k sum_j g_j - g_k; the same form holds for the float32
+          // deviations from the uniform state
+          double gk[Q];
+          double sum = 0.0;
+#pragma unroll
+          for (int k = 0; k < Q; ++k) {
+            gk[k] = static_cast<double>(g[k * ps + node]);
+            sum += gk[k];
+          }
+#pragma unroll
+          for (int k = 0; k < Q; ++k) z[k] = p.omega[k] * sum - gk[k];
+        }
+#pragma unroll
+        for (int k = 0; k < Q; ++k) acc += static_cast<double>(mu[k]) * z[k];
+      }
+    }
+  }
+  if (g) block_sum(acc, sh, partial + blockIdx.x, true);
+}
+
+// Seed lambda^N_k(x) = dL/dphi^N(x) for every k.
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_adjoint_seed(const double* __restrict__ dldphi, T* __restrict__ lam, const KParams p) {
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
+       node += gridDim.x * blockDim.x) {
+    const T v = static_cast<T>(dldphi[node]);
+    for (int k = 0; k < p.q; ++k) lam[k * p.pstride + node] = v;
+  }
+}
+
+// Transpose of the initialisation f_k = omega_k [phi0 + tau dt (u - c_k) . grad phi0]:
+//   dL/dphi0 (direct part)  = sum_k omega_k lambda_k
+//   dL/d(grad phi0)_a       = tau dt sum_k omega_k (u_a - c_ka) lambda_k
+// and the tau-derivative of the initial state, (f^0_k - omega_k phi0) / tau,
+// contracted with lambda^0 (per-block partial sums).  g0 is the stored initial
+// state (post-collision, or split).
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_adjoint_init(const T* __restrict__ lam, const T* __restrict__ g0,
+                   const double* __restrict__ g0phi, const KParams p, const int mode,
+                   double* __restrict__ dphi, double* __restrict__ dgrad,
+                   double* __restrict__ partial) {
+  constexpr int Q = q_of(D);
+  __shared__ double sh[256];
+  double acc = 0.0;
+  const long long ps = p.pstride;
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
+       node += gridDim.x * blockDim.x) {
+    double l[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) l[k] = static_cast<double>(lam[k * ps + node]);
+    double s0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) s0 += p.omega[k] * l[k];
+    dphi[node] = s0;
+    if (dgrad) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double h = 0.0;
+        sfor<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr CV4 c = cvec(D, k);
+          h += p.omega[k] * (p.u[a] - c.v[a]) * l[k];
+        });
+        dgrad[(long long)a * p.nodes + node] = p.tau * p.dt * h;
+      }
+    }
+    // f^0_k - omega_k phi0
+    double z[Q];
+    if (mode == kSplit) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) z[k] = static_cast<double>(g0[k * ps + node]);
+    } else {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) sum += static_cast<double>(g0[k * ps + node]);
+      // post-collision g = C f + b:  f_k - omega_k phi = (g_k - b_k - omega_k phi)/(1-s),
+      // phi = sum g - dt R; in deviation form (g_k - omega_k sum_j g_j)/(1-s)
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        z[k] = (static_cast<double>(g0[k * ps + node]) - p.omega[k] * sum) / (1.0 - p.s);
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) acc += l[k] * z[k];
+  }
+  (void)g0phi;
+  block_sum(acc / p.tau, sh, partial + blockIdx.x);
+}
+
+// dphi -= sum_a D_a(dgrad_a), D_a the fourth-order central difference on the
+// periodic grid (its transpose is -D_a).
+template <int D>
+__global__ void __launch_bounds__(256)
+    k_adjoint_fd(const double* __restrict__ dgrad, double* __restrict__ dphi, const KParams p) {
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
+       node += gridDim.x * blockDim.x) {
+    int i[D];
+    int rr = node;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      i[a] = rr % p.n[a];
+      rr /= p.n[a];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int n = p.n[a];
+      const int st = p.stride[a];
+      const double* h = dgrad + (long long)a * p.nodes;
+      auto at = [&](int s) {
+        int j = i[a] + s;
+        j = (j % n + n) % n;
+        return h[node + (j - i[a]) * st];
+      };
+      acc += (-at(2) + 8.0 * at(1) - 8.0 * at(-1) + at(-2)) / (12.0 * p.dx);
+    }
+    dphi[node] -= acc;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_sum_partials(const double* __restrict__ partial, long long n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (long long b = threadIdx.x; b < n; b += blockDim.x) acc += partial[b];
+  block_sum(acc, sh, out);
+}
+
+// --------------------------------------------------------------- launchers --
+
+template <int D>
+static hipError_t adjoint_d(const KParams& p, int mode, const void* lsrc, void* ldst,
+                            const void* g, const double* gphi, double* partial,
+                            hipStream_t stream) {
+  const LaunchShape s = step_shape(p);
+  const dim3 block(s.tx, s.ty), grid(s.blocks);
+  if (mode == kFP64)
+    hipLaunchKernelGGL((k_adjoint<D, double>), grid, block, 0, stream,
+                       static_cast<const double*>(lsrc), static_cast<double*>(ldst),
+                       static_cast<const double*>(g), gphi, p, mode, partial);
+  else
+    hipLaunchKernelGGL((k_adjoint<D, float>), grid, block, 0, stream,
+                       static_cast<const float*>(lsrc), static_cast<float*>(ldst),
+                       static_cast<const float*>(g), gphi, p, mode, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const KParams& p, int mode, const void* lsrc, void* ldst,
+                               const void* g, const double* gphi, double* partial,
+                               hipStream_t stream) {
+  switch (p.d) {
+    case 1: return adjoint_d<1>(p, mode, lsrc, ldst, g, gphi, partial, stream);
+    case 2: return adjoint_d<2>(p, mode, lsrc, ldst, g, gphi, partial, stream);
+    case 3: return adjoint_d<3>(p, mode, lsrc, ldst, g, gphi, partial, stream);
+    case 4: return adjoint_d<4>(p, mode, lsrc, ldst, g, gphi, partial, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static unsigned node_grid(long long nodes) {
+  long long b = (nodes + 255) / 256;
+  if (b > 65536) b = 65536;
+  return static_cast<unsigned>(b < 1 ? 1 : b);
+}
+
+hipError_t launch_adjoint_seed(const KParams& p, int mode, const double* dldphi, void* lam,
+                               hipStream_t stream) {
+  if (mode == kFP64)
+    hipLaunchKernelGGL((k_adjoint_seed<double>), dim3(node_grid(p.nodes)), dim3(256), 0, stream,
+                       dldphi, static_cast<double*>(lam), p);
+  else
+    hipLaunchKernelGGL((k_adjoint_seed<float>), dim3(node_grid(p.nodes)), dim3(256), 0, stream,
+                       dldphi, static_cast<float*>(lam), p);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t adjoint_init_d(const KParams& p, int mode, const void* lam, const void* g0,
+                                 const double* g0phi, double* dphi, double* dgrad,
+                                 bool fd, double* partial, hipStream_t stream) {
+  const dim3 grid(node_grid(p.nodes)), block(256);
+  if (mode == kFP64)
+    hipLaunchKernelGGL((k_adjoint_init<D, double>), grid, block, 0, stream,
+                       static_cast<const double*>(lam), static_cast<const double*>(g0), g0phi,
+                       p, mode, dphi, dgrad, partial);
+  else
+    hipLaunchKernelGGL((k_adjoint_init<D, float>), grid, block, 0, stream,
+                       static_cast<const float*>(lam), static_cast<const float*>(g0), g0phi, p,
+                       mode, dphi, dgrad, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !fd) return e;
+  hipLaunchKernelGGL((k_adjoint_fd<D>), grid, block, 0, stream, dgrad, dphi, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init(const KParams& p, int mode, const void* lam, const void* g0,
+                               const double* g0phi, double* dphi, double* dgrad, bool fd,
+                               double* partial, unsigned* nblocks, hipStream_t stream) {
+  *nblocks = node_grid(p.nodes);
+  switch (p.d) {
+    case 1: return adjoint_init_d<1>(p, mode, lam, g0, g0phi, dphi, dgrad, fd, partial, stream);
+    case 2: return adjoint_init_d<2>(p, mode, lam, g0, g0phi, dphi, dgrad, fd, partial, stream);
+    case 3: return adjoint_init_d<3>(p, mode, lam, g0, g0phi, dphi, dgrad, fd, partial, stream);
+    case 4: return adjoint_init_d<4>(p, mode, lam, g0, g0phi, dphi, dgrad, fd, partial, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sum_partials(const double* partial, long long n, double* out,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, stream, partial, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -4,6 +4,7 @@
 // stream-ordered launch sequence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -36,6 +37,13 @@ struct lbm_handle {
   int64_t step = 0;
   bool initialised = false;
   std::string err;
+  // how the current state was initialised (gradients w.r.t. phi0 need it)
+  int init_kind = 0;  // 0 unknown, 1 analytic field, 2 device phi0 + FD gradient,
+                      // 3 device phi0 + explicit gradient, 4 K = 1
+  // tape of checkpoints for lbm_tape_gradient
+  bool tape_active = false;
+  int64_t tape_start = 0, tape_every = 0;
+  std::vector<void*> tape_ckpt;
   // kernel timing (lbm_profile_begin / lbm_profile_end): 3 events per step
   std::vector<hipEvent_t> prof_ev;
   int64_t prof_cap = 0, prof_used = 0;
@@ -189,6 +197,45 @@ int compute_reference(lbm_handle* h, const double* phi0) {
   if (rc != LBM_OK) return rc;
   h->kp.phi_ref = host[0] / static_cast<double>(h->nodes);
   return LBM_OK;
+}
+
+size_t state_bytes(const lbm_handle* h) {
+  return pop_bytes(h) + (h->precision == LBM_FP32_SPLIT ? phi_bytes(h) : 0);
+}
+
+// Device copy of the current state into a buffer of state_bytes(h).
+hipError_t copy_state_out(lbm_handle* h, void* dst) {
+  hipError_t e = hipMemcpyAsync(dst, h->buf[h->cur], pop_bytes(h), hipMemcpyDeviceToDevice,
+                                h->stream);
+  if (e == hipSuccess && h->precision == LBM_FP32_SPLIT)
+    e = hipMemcpyAsync(static_cast<char*>(dst) + pop_bytes(h), h->phib[h->cur], phi_bytes(h),
+                       hipMemcpyDeviceToDevice, h->stream);
+  return e;
+}
+
+double* blob_phi(const lbm_handle* h, void* blob) {
+  return h->precision == LBM_FP32_SPLIT
+             ? reinterpret_cast<double*>(static_cast<char*>(blob) + pop_bytes(h))
+             : nullptr;
+}
+
+int tape_push(lbm_handle* h) {
+  void* b = dev_alloc(h, state_bytes(h));
+  if (!b) return fail(h, LBM_ENOMEM, "checkpoint allocation failed");
+  hipError_t e = copy_state_out(h, b);
+  if (e != hipSuccess) {
+    dev_free(h, b);
+    return hip_fail(h, e, "checkpoint copy");
+  }
+  h->tape_ckpt.push_back(b);
+  return LBM_OK;
+}
+
+void tape_clear(lbm_handle* h) {
+  (void)hipStreamSynchronize(h->stream);
+  for (void* b : h->tape_ckpt) dev_free(h, b);
+  h->tape_ckpt.clear();
+  h->tape_active = false;
 }
 
 }  // namespace
@@ -373,6 +420,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
       return rc;
     }
     h->initialised = true;
+    h->init_kind = (p->init_order == 1) ? 4 : 1;
   }
   h->cur = 0;
   h->step = 0;
@@ -396,6 +444,7 @@ int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_ph
   h->cur = 0;
   h->step = 0;
   h->initialised = true;
+  h->init_kind = (h->kp.K == 1) ? 4 : (grad_phi0_dev ? 3 : 2);
   return LBM_OK;
 }
 
@@ -415,6 +464,10 @@ int lbm_step(lbm_handle* h, int64_t n) {
     if (e != hipSuccess) return hip_fail(h, e, "step kernel");
     h->cur = dst;
     ++h->step;
+    if (h->tape_active && (h->step - h->tape_start) % h->tape_every == 0) {
+      int rc = tape_push(h);
+      if (rc != LBM_OK) return rc;
+    }
   }
   return LBM_OK;
 }
@@ -495,6 +548,7 @@ int lbm_set_state(lbm_handle* h, const void* src_dev, int64_t step) {
   if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync");
   h->step = step;
   h->initialised = true;
+  h->init_kind = 0;
   return LBM_OK;
 }
 
@@ -553,6 +607,147 @@ int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* st
   return LBM_OK;
 }
 
+int lbm_tape_begin(lbm_handle* h, int64_t every) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+  if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state");
+  if (every < 1) return fail(h, LBM_EINVAL, "checkpoint interval must be >= 1");
+  tape_clear(h);
+  h->tape_start = h->step;
+  h->tape_every = every;
+  h->tape_active = true;
+  int rc = tape_push(h);
+  if (rc != LBM_OK) h->tape_active = false;
+  return rc;
+}
+
+int lbm_tape_end(lbm_handle* h) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+  tape_clear(h);
+  return LBM_OK;
+}
+
+int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0_dev,
+                      double* dl_dgrad0_dev, double* dl_dtau_host) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+  if (!h->tape_active) return fail(h, LBM_EINVAL, "no active tape (call lbm_tape_begin)");
+  if (!dl_dphi_dev) return fail(h, LBM_EINVAL, "dL/dphi is NULL");
+  const bool want_init = dl_dphi0_dev || dl_dgrad0_dev;
+  const bool at_init = h->tape_start == 0 && h->init_kind != 0;
+  if (want_init && !at_init)
+    return fail(h, LBM_EINVAL, "initial-state gradients need a tape that starts at an initialisation");
+  if (dl_dtau_host && h->precision != LBM_FP32_SPLIT && h->kp.s == 1.0)
+    return fail(h, LBM_EUNSUPPORTED, "dL/dtau needs s != 1 with post-collision storage");
+  const KParams& kp = h->kp;
+  const int64_t N = h->step - h->tape_start;
+  const int64_t K = h->tape_every;
+  const int64_t nseg = (N + K - 1) / K;
+  const bool want_tau = dl_dtau_host != nullptr;
+  const size_t pb = pop_bytes(h), sb = state_bytes(h);
+  const LaunchShape shp = step_shape(kp);
+
+  std::vector<void*> owned;
+  auto alloc = [&](size_t bytes) -> void* {
+    void* b = dev_alloc(h, bytes);
+    if (b) owned.push_back(b);
+    return b;
+  };
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(h->stream);
+    for (void* b : owned) dev_free(h, b);
+    owned.clear();
+  };
+  void* lam[2] = {alloc(pb), alloc(pb)};
+  double* partial = static_cast<double*>(alloc(sizeof(double) * (shp.blocks + 65536)));
+  // dsteps[0]: sum over the steps of the dL/ds contractions; dsteps[1]: the
+  // initialisation's tau term
+  double* dsteps = static_cast<double*>(alloc(sizeof(double) * 2));
+  double* partial_init = static_cast<double*>(alloc(sizeof(double) * 65536));
+  std::vector<void*> seg;
+  if (want_tau && N > 0)
+    for (int64_t i = 1; i < std::min<int64_t>(K, N); ++i) seg.push_back(alloc(sb));
+  bool ok = lam[0] && lam[1] && partial && dsteps && partial_init;
+  for (void* b : seg) ok = ok && b;
+  if (!ok) {
+    cleanup();
+    return fail(h, LBM_ENOMEM, "adjoint buffers");
+  }
+  hipError_t e = hipMemsetAsync(lam[0], 0, pb, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(lam[1], 0, pb, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(partial, 0, sizeof(double) * shp.blocks, h->stream);
+  if (e == hipSuccess) e = launch_adjoint_seed(kp, h->precision, dl_dphi_dev, lam[0], h->stream);
+  int cur = 0;
+  for (int64_t sgi = nseg - 1; sgi >= 0 && e == hipSuccess; --sgi) {
+    const int64_t s0 = h->tape_start + sgi * K;
+    const int64_t s1 = std::min<int64_t>(s0 + K, h->step);
+    // forward states g^{s0} .. g^{s1-1} of this segment (only for dL/dtau)
+    std::vector<void*> st;
+    if (want_tau) {
+      st.push_back(h->tape_ckpt[sgi]);
+      for (int64_t n = s0 + 1; n < s1 && e == hipSuccess; ++n) {
+        void* src = st.back();
+        void* dst = seg[n - s0 - 1];
+        e = launch_step(kp, h->precision, src, dst, blob_phi(h, src), blob_phi(h, dst), n - 1,
+                        h->stream);
+        st.push_back(dst);
+      }
+    }
+    for (int64_t n = s1 - 1; n >= s0 && e == hipSuccess; --n) {
+      const void* g = want_tau ? st[n - s0] : nullptr;
+      e = launch_adjoint_step(kp, h->precision, lam[cur], lam[1 - cur], g,
+                              want_tau ? blob_phi(h, const_cast<void*>(g)) : nullptr, partial,
+                              h->stream);
+      cur = 1 - cur;
+    }
+  }
+  // dL/ds (without the 1/(1-s) of the post-collision modes), summed over the steps
+  if (e == hipSuccess && want_tau) e = launch_sum_partials(partial, shp.blocks, dsteps, h->stream);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(h, e, "adjoint kernels");
+  }
+  // lambda^{start} = dL/df at the start of the tape
+  double init_tau = 0.0;
+  if (want_init || (want_tau && at_init)) {
+    const bool fd = h->init_kind == 2;
+    double* dphi = dl_dphi0_dev ? dl_dphi0_dev : static_cast<double*>(alloc(phi_bytes(h)));
+    double* dgrad = dl_dgrad0_dev;
+    if (!dgrad && fd) dgrad = static_cast<double*>(alloc(phi_bytes(h) * h->d));
+    if (!dphi || (fd && !dgrad)) {
+      cleanup();
+      return fail(h, LBM_ENOMEM, "adjoint buffers");
+    }
+    unsigned nb = 0;
+    e = launch_adjoint_init(kp, h->precision, lam[cur], h->tape_ckpt[0],
+                            blob_phi(h, h->tape_ckpt[0]), dphi, dgrad, fd, partial_init, &nb,
+                            h->stream);
+    if (e == hipSuccess) e = launch_sum_partials(partial_init, nb, dsteps + 1, h->stream);
+    if (e != hipSuccess) {
+      cleanup();
+      return hip_fail(h, e, "adjoint initialisation kernel");
+    }
+    if (h->kp.K == 3 && want_tau) {
+      e = hipMemcpyAsync(&init_tau, dsteps + 1, sizeof(double), hipMemcpyDeviceToHost,
+                         h->stream);
+    }
+  }
+  if (want_tau && e == hipSuccess) {
+    double dlds = 0.0;
+    e = hipMemcpyAsync(&dlds, dsteps, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) {
+      if (h->precision != LBM_FP32_SPLIT) dlds /= (1.0 - kp.s);
+      // s = 1/tau
+      *dl_dtau_host = -dlds / (kp.tau * kp.tau) + (at_init ? init_tau : 0.0);
+    }
+  }
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(h, e, "adjoint readback");
+  }
+  cleanup();
+  return LBM_OK;
+}
+
 int lbm_equilibrium_weights(int d, const double* u, double g, int use_m4, double m4,
                             double* omega_out, double* m4_out, double* min_omega_out) {
   if (d < 1 || d > kMaxDim || !u || !omega_out)
@@ -575,6 +770,7 @@ int lbm_destroy(lbm_handle* h) {
   if (!h) return LBM_OK;
   (void)hipStreamSynchronize(h->stream);
   destroy_events(h);
+  tape_clear(h);
   release(h);
   delete h;
   return LBM_OK;

@@ -100,4 +100,21 @@ hipError_t launch_moments(const KParams& p, int mode, const void* f, const doubl
 hipError_t launch_sum_phi0(const KParams& p, const double* arr, double* partial,
                            double* out, hipStream_t stream);
 
+// Adjoint step lambda^{n+1} -> lambda^n (adjoint.hip).  g: forward state at
+// step n (nullable); when given, per-block partial sums of
+// <nu^n, (omega 1^T - I) f^n> (without the 1/(1-s) factor of the
+// post-collision modes) go to partial[0 .. step_shape(p).blocks).
+hipError_t launch_adjoint_step(const KParams& p, int mode, const void* lsrc, void* ldst,
+                               const void* g, const double* gphi, double* partial,
+                               hipStream_t stream);
+hipError_t launch_adjoint_seed(const KParams& p, int mode, const double* dldphi, void* lam,
+                               hipStream_t stream);
+// Transpose of the initialisation; partial[0 .. *nblocks) receives the
+// contraction of lambda^0 with d f^0 / d tau.
+hipError_t launch_adjoint_init(const KParams& p, int mode, const void* lam, const void* g0,
+                               const double* g0phi, double* dphi, double* dgrad, bool fd,
+                               double* partial, unsigned* nblocks, hipStream_t stream);
+hipError_t launch_sum_partials(const double* partial, long long n, double* out,
+                               hipStream_t stream);
+
 }  // namespace lbm

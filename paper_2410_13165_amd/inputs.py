@@ -73,6 +73,31 @@ def noise(shape: Sequence[int], seed: int, std: float = 1e-3) -> np.ndarray:
     return np.random.default_rng(seed).normal(0.0, std, size=tuple(shape))
 
 
+def gaussian_random_field(n: int, d: int, seed: int, corr: float = 0.1) -> np.ndarray:
+    """Periodic Gaussian random field on [0,1)^d with n nodes per axis: white
+    noise filtered by sqrt(exp(-|k|^2 corr^2 / 2)) in Fourier space, scaled to unit
+    variance.  Returned in C order of shape (n,)*d (any axis order: isotropic)."""
+    rng = np.random.default_rng(seed)
+    w = rng.normal(size=(n,) * d)
+    W = np.fft.rfftn(w)
+    k1 = 2.0 * np.pi * np.fft.fftfreq(n, d=1.0 / n)
+    kr = 2.0 * np.pi * np.fft.rfftfreq(n, d=1.0 / n)
+    grids = np.meshgrid(*([k1] * (d - 1) + [kr]), indexing="ij", sparse=True)
+    k2 = sum(g * g for g in grids)
+    W *= np.sqrt(np.exp(-0.5 * k2 * corr * corr))
+    f = np.fft.irfftn(W, s=(n,) * d)
+    f -= f.mean()
+    return f / f.std()
+
+
+# Gradient workload: D3Q19 on the periodic unit cube with 256 nodes per axis,
+# u = (0.05, 0.1, 0.08), tau = 1/2, R = 0, 1000 float32 steps from a Gaussian
+# random field (correlation length 0.1, seed 5), misfit to another field (seed 6),
+# checkpoints every 32 steps.
+ADJOINT_D3Q19 = {"d": 3, "n": 256, "u": [0.05, 0.1, 0.08], "steps": 1000, "every": 32,
+                 "seed_init": 5, "seed_target": 6, "corr": 0.1}
+
+
 # Workload of the benchmark: D3Q19 on the unit cube, 512 nodes per axis,
 # full-way Dirichlet walls on all six faces with data from four random cosines
 # (seed 3), u = (0.05, 0.1, 0.08) (Table 3), R = 1, K = 3, P = 4.

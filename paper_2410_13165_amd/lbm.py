@@ -78,6 +78,10 @@ SIGNATURES = {
     "lbm_equilibrium_weights": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.c_double, C.c_int,
                                            C.c_double, C.POINTER(C.c_double),
                                            C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lbm_tape_begin": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_tape_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.POINTER(C.c_double)]),
+    "lbm_tape_end": (C.c_int, [C.c_void_p]),
     "lbm_profile_begin": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(C.c_int64)]),
@@ -294,6 +298,37 @@ class Lattice:
             "s": inf.s, "dt": inf.dt, "phi_ref": inf.phi_ref, "bytes_per_lu": inf.bytes_per_lu,
             "pstride": inf.pstride,
         }
+
+    def tape_begin(self, every: int):
+        self._check(self.lib.lbm_tape_begin(self._h, int(every)))
+        return self
+
+    def tape_end(self):
+        self._check(self.lib.lbm_tape_end(self._h))
+        return self
+
+    def tape_gradient(self, dl_dphi, want_phi0: bool = True, want_grad0: bool = False,
+                      want_tau: bool = True) -> dict:
+        """Adjoint gradients of L given dL/dphi^N (shape (N_d, ..., N_1))."""
+        torch = self._torch
+        seed = dl_dphi.to(device=self.device, dtype=torch.float64).contiguous()
+        gphi = torch.empty(self.nodes, dtype=torch.float64, device=self.device) if want_phi0 else None
+        ggrad = (torch.empty(self.d * self.nodes, dtype=torch.float64, device=self.device)
+                 if want_grad0 else None)
+        tau = C.c_double()
+        self._check(self.lib.lbm_tape_gradient(
+            self._h, C.c_void_p(seed.data_ptr()),
+            C.c_void_p(gphi.data_ptr()) if gphi is not None else None,
+            C.c_void_p(ggrad.data_ptr()) if ggrad is not None else None,
+            C.byref(tau) if want_tau else None))
+        out = {}
+        if gphi is not None:
+            out["phi0"] = gphi.view(*reversed(self.dims))
+        if ggrad is not None:
+            out["grad0"] = ggrad.view(self.d, *reversed(self.dims))
+        if want_tau:
+            out["tau"] = tau.value
+        return out
 
     def profile_begin(self, max_steps: int):
         self._check(self.lib.lbm_profile_begin(self._h, int(max_steps)))

@@ -1,0 +1,206 @@
+"""GPU adjoint (transposed stream-collide) against the oracle.
+
+The scheme is linear in the initial field, so the gradient of
+L = 1/2 sum_x (phi^N - target)^2 is J^T (phi^N - target), J the Jacobian of
+phi0 -> phi^N.  The oracle's J is built column by column from unit initial
+fields (its transpose is then exact, no finite-difference error); dL/dtau is
+checked against a central difference of the oracle in tau.  At larger sizes the
+GPU gradient is checked against central differences of the GPU forward run in
+random directions, which are exact up to rounding because L is quadratic.
+"""
+import numpy as np
+import pytest
+
+from oracle import lbm_oracle as O
+from paper_2410_13165_amd import inputs
+from tests.pairs import gpu_lattice, oracle_problem, to_oracle_order
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _oracle_map(d, dims, dx, spec, bc, tau, K, steps, phi0, grad0=None, fd=False):
+    prob = oracle_problem(d, dims, dx, spec, u=spec["u"] if spec else None, tau=tau, bc=bc, K=K)
+    if fd:
+        grad0 = O.fd4_gradient(phi0, dx)  # what the GPU does for an initial state without gradient
+    run = O.Run(prob, phi0=phi0, grad0=grad0)
+    return run.step(steps).phi()
+
+
+def _jacobians(d, dims, dx, spec, bc, tau, K, steps, with_grad):
+    """Columns of d phi^N / d phi0 (and / d grad phi0) from the oracle."""
+    nodes = int(np.prod(dims))
+    zero = np.zeros(dims)
+    zg = np.zeros(dims + (d,))
+    fd = not with_grad
+    base = _oracle_map(d, dims, dx, spec, bc, tau, K, steps, zero, zg, fd)
+    Jphi = np.empty((nodes, nodes))
+    for i in range(nodes):
+        e = np.zeros(nodes)
+        e[i] = 1.0
+        Jphi[:, i] = (_oracle_map(d, dims, dx, spec, bc, tau, K, steps, e.reshape(dims), zg, fd)
+                      - base).ravel()
+    Jg = None
+    if with_grad:
+        Jg = np.empty((d, nodes, nodes))
+        for a in range(d):
+            for i in range(nodes):
+                g = np.zeros(dims + (d,))
+                g.reshape(nodes, d)[i, a] = 1.0
+                Jg[a, :, i] = (_oracle_map(d, dims, dx, spec, bc, tau, K, steps, zero, g, fd)
+                               - base).ravel()
+    return Jphi, Jg
+
+
+def _gpu_gradient(d, dims, dx, spec, bc, tau, K, steps, every, phi0, grad0, target, prec="fp64",
+                  want_tau=True):
+    lat = gpu_lattice(d, dims, dx, spec, u=spec["u"], tau=tau, bc=bc, K=K, precision=prec)
+    try:
+        gl = lambda a: torch.from_numpy(np.ascontiguousarray(a.T).ravel())
+        if grad0 is None:
+            lat.set_initial(gl(phi0))
+        else:
+            g = np.stack([np.ascontiguousarray(grad0[..., a].T) for a in range(d)])
+            lat.set_initial(gl(phi0), torch.from_numpy(g.ravel()))
+        lat.tape_begin(every)
+        lat.step(steps)
+        phiN = lat.phi()
+        tgt = torch.from_numpy(np.ascontiguousarray(target.T)).to(phiN.device)
+        res = (phiN - tgt)
+        out = lat.tape_gradient(res, want_phi0=True, want_grad0=grad0 is not None,
+                                want_tau=want_tau)
+        out["res"] = to_oracle_order(res.cpu().numpy())
+        out["L"] = 0.5 * float((res ** 2).sum())
+        out["phi0"] = to_oracle_order(out["phi0"].cpu().numpy())
+        if "grad0" in out:
+            g = out["grad0"].cpu().numpy()
+            out["grad0"] = np.stack([to_oracle_order(g[a]) for a in range(d)], axis=-1)
+        lat.tape_end()
+        return out
+    finally:
+        lat.close()
+
+
+CASES = [
+    # d, dims, bc, K, with explicit gradient
+    (2, (9, 7), ["periodic"] * 2, 3, False),
+    (2, (8, 6), ["periodic"] * 2, 1, False),
+    (2, (7, 8), ["fullway"] * 2, 3, True),
+    (2, (7, 6), ["halfway"] * 2, 3, True),
+    (3, (5, 4, 4), ["periodic"] * 3, 3, False),
+    (3, (5, 5, 4), ["fullway"] * 3, 3, True),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("tau", [0.5, 0.7])
+def test_adjoint_equals_oracle_transpose(case, tau):
+    d, dims, bc, K, with_grad = CASES[case]
+    spec = inputs.random_cosines(d, [0.12, -0.07, 0.05][:d], 0.3, seed=90 + case, kmax=1.0)
+    dx = 0.1
+    steps, every = 5, 2
+    rng = np.random.default_rng(100 + case)
+    phi0 = rng.normal(size=dims)
+    grad0 = rng.normal(size=dims + (d,)) if with_grad else None
+    target = rng.normal(size=dims)
+    print(f"[adjoint] d={d} dims={dims} bc={bc[0]} K={K} tau={tau}", flush=True)
+    out = _gpu_gradient(d, dims, dx, spec, bc, tau, K, steps, every, phi0, grad0, target)
+    Jphi, Jg = _jacobians(d, dims, dx, spec, bc, tau, K, steps, with_grad)
+    res = out["res"].ravel()
+    want = (Jphi.T @ res).reshape(dims)
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(out["phi0"] - want)) <= 1e-12 * scale
+    if with_grad:
+        for a in range(d):
+            wg = (Jg[a].T @ res).reshape(dims)
+            # dL/dgrad carries the factor tau dt, so compare on the phi0 gradient's scale
+            assert np.max(np.abs(out["grad0"][..., a] - wg)) <= 1e-12 * scale
+    # dL/dtau against a central difference of the oracle
+    h = 1e-5
+
+    def L_or(t):
+        phi = _oracle_map(d, dims, dx, spec, bc, t, K, steps, phi0, grad0, fd=not with_grad)
+        return 0.5 * float(np.sum((phi - target) ** 2))
+    fd_tau = (L_or(tau + h) - L_or(tau - h)) / (2 * h)
+    assert abs(out["tau"] - fd_tau) <= 1e-6 * max(1.0, abs(fd_tau)), (out["tau"], fd_tau)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_split", 1e-5)])
+def test_gradient_against_gpu_finite_differences(prec, tol):
+    """D3Q19 periodic 32^3, 40 steps, checkpoints every 8: <dL/dphi0, v> against
+    (L(phi0 + h v) - L(phi0 - h v)) / 2h in 6 random directions (exact for a
+    quadratic L up to rounding)."""
+    d, dims = 3, (32, 32, 32)
+    spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 0.0, seed=5)
+    dx = 1.0 / 32
+    rng = np.random.default_rng(6)
+    phi0 = rng.normal(size=dims)
+    target = rng.normal(size=dims)
+    out = _gpu_gradient(d, dims, dx, spec, ["periodic"] * 3, 0.5, 3, 40, 8, phi0, None, target,
+                        prec=prec, want_tau=False)
+    lat = gpu_lattice(d, dims, dx, spec, u=spec["u"], precision="fp64")
+    try:
+        def L(phi):
+            lat.set_initial(torch.from_numpy(np.ascontiguousarray(phi.T).ravel()))
+            lat.step(40)
+            p = to_oracle_order(lat.phi().cpu().numpy())
+            return 0.5 * float(np.sum((p - target) ** 2))
+        for i in range(6):
+            v = np.random.default_rng(100 + i).normal(size=dims)
+            h = 1.0
+            fd = (L(phi0 + h * v) - L(phi0 - h * v)) / (2 * h)
+            ad = float(np.sum(out["phi0"] * v))
+            assert abs(ad - fd) <= tol * abs(fd), (i, ad, fd)
+    finally:
+        lat.close()
+
+
+def test_tape_errors_and_state_unchanged():
+    from paper_2410_13165_amd import LbmError
+    spec = inputs.random_cosines(2, [0.1, 0.1], 0.0, seed=7)
+    lat = gpu_lattice(2, (16, 16), 1.0 / 16, spec)
+    try:
+        seed = torch.zeros(16, 16, dtype=torch.float64, device="cuda")
+        with pytest.raises(LbmError, match="tape"):
+            lat.tape_gradient(seed)
+        lat.tape_begin(3)
+        lat.step(7)
+        before = lat.phi().clone()
+        lat.tape_gradient(seed)
+        assert torch.equal(before, lat.phi())
+        assert lat.info()["step"] == 7
+        st = lat.get_state().clone()
+        lat.set_state(st, 7)
+        lat.tape_begin(3)
+        lat.step(2)
+        with pytest.raises(LbmError, match="initialisation"):
+            lat.tape_gradient(seed)
+        lat.tape_gradient(seed, want_phi0=False, want_tau=True)
+    finally:
+        lat.close()
+
+
+def test_autograd_function_matches_finite_differences():
+    from paper_2410_13165_amd.autograd import Evolve
+    d, dims = 2, (48, 40)
+    spec = inputs.random_cosines(2, [0.1, -0.15], 0.0, seed=8)
+    kw = dict(d=d, dims=dims, dx=1.0 / 48, u=spec["u"], precision="fp64")
+    rng = np.random.default_rng(9)
+    phi0 = torch.from_numpy(rng.normal(size=tuple(reversed(dims)))).cuda().requires_grad_(True)
+    tau = torch.tensor(0.6, dtype=torch.float64, requires_grad=True)
+    tgt = torch.from_numpy(rng.normal(size=tuple(reversed(dims)))).cuda()
+    phiN = Evolve.apply(phi0, tau, kw, 30, 7)
+    loss = 0.5 * (phiN - tgt).pow(2).sum()
+    loss.backward()
+
+    def L(p, t):
+        with torch.no_grad():
+            return float(0.5 * (Evolve.apply(p, torch.tensor(t, dtype=torch.float64), kw, 30, 7)
+                                - tgt).pow(2).sum())
+    v = torch.from_numpy(rng.normal(size=tuple(reversed(dims)))).cuda()
+    fd = (L(phi0.detach() + v, 0.6) - L(phi0.detach() - v, 0.6)) / 2
+    assert abs(float((phi0.grad * v).sum()) - fd) <= 1e-9 * abs(fd)
+    h = 1e-5
+    fdt = (L(phi0.detach(), 0.6 + h) - L(phi0.detach(), 0.6 - h)) / (2 * h)
+    assert abs(float(tau.grad) - fdt) <= 1e-6 * max(1.0, abs(fdt))
