@@ -160,6 +160,51 @@ def run_adjoint(precision: str = "fp32", n=None, steps=None):
     }
 
 
+def run_sweep(steps=None, count=None, precision="fp32"):
+    """512 independent D2Q9 lattices advanced together (tuned launch form);
+    per-instance growth of the L2 norm of phi."""
+    import numpy as np
+    import torch
+    from paper_2410_13165_amd import Batch, inputs
+    w = inputs.SWEEP_D2Q9
+    steps = steps or w["steps"]
+    specs = inputs.sweep_specs(count)
+    phi0 = torch.from_numpy(inputs.sweep_phi0(specs))
+    nodes = sum(int(np.prod(sp["dims"])) for sp in specs)
+    print(f"# sweep: {len(specs)} lattices, {nodes} nodes", file=sys.stderr, flush=True)
+    with Batch(2, specs, precision=precision) as b:
+        b.set_initial(phi0)
+        print("# sweep: initialised", file=sys.stderr, flush=True)
+        cfg = b.tune(10)
+        print(f"# sweep: tuned {cfg}", file=sys.stderr, flush=True)
+        m0 = b.moments()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chunk = 500
+        for done in range(0, steps, chunk):
+            b.step(min(chunk, steps - done))
+            torch.cuda.synchronize()
+            print(f"# sweep: {min(done + chunk, steps)} steps", file=sys.stderr, flush=True)
+        t1 = time.perf_counter()
+        m1 = b.moments()
+        min_om = np.array([b.instance(i).info()["min_omega"] for i in range(len(specs))])
+    taus = np.array([sp["tau"] for sp in specs])
+    growth = np.sqrt(m1[:, 1] / m0[:, 1])
+    s2 = np.isclose(taus, 0.5)
+    finite = np.isfinite(growth)
+    return {
+        "workload": (f"{len(specs)} periodic D2Q9 lattices (sizes 64^2..512^2), {precision}, "
+                     f"{steps} steps, tau~U(0.5,2), sigma~U(-0.75,0.75)^2, noise init"),
+        "nodes": nodes,
+        "seconds": t1 - t0,
+        "mlups": nodes * steps / (t1 - t0) / 1e6,
+        "config": cfg,
+        "grew_1e3": int(np.sum(~finite | (growth > 1e3))),
+        "bounded": int(np.sum(finite & (growth <= 1.0 + 1e-6))),
+        "entropy_stable_instances": int(np.sum(min_om > 0)),
+    }
+
+
 def cpu_baseline(n_sample: int, steps: int):
     """The FP64 oracle on a bounded sample: a cube of n_sample^3 nodes with the
     benchmark's spacing, field and walls, for `steps` steps."""
@@ -196,6 +241,7 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args(argv)
@@ -230,6 +276,11 @@ def main(argv=None):
         print(f"# {m}: {results[m]['mlups']:.0f} MLUPS, bulk {results[m]['bulk_gbs']:.0f} GB/s, "
               f"rmse {results[m]['rmse']:.3e}", file=sys.stderr, flush=True)
     head = results[modes[0]]
+    sweep = None
+    if not args.no_sweep:
+        sweep = run_sweep()
+        print(f"# sweep: {sweep['mlups']:.0f} MLUPS, config {sweep['config']}", file=sys.stderr,
+              flush=True)
     adj = None
     if not args.no_adjoint:
         adj = run_adjoint("fp32")
@@ -280,6 +331,7 @@ def main(argv=None):
         "modes": {m: {k: (float(f"{v:.6g}") if isinstance(v, float) else v)
                       for k, v in r.items()}
                   for m, r in results.items()},
+        "sweep": sweep,
         "adjoint_fwd_ratio": round(adj["ratio"], 4) if adj else None,
         "adjoint": ({k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in adj.items()}
                     if adj else None),

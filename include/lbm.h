@@ -243,6 +243,35 @@ int lbm_tape_end(lbm_handle* h);
 int lbm_equilibrium_weights(int d, const double* u, double g, int use_m4, double m4,
                             double* omega_out, double* m4_out, double* min_omega_out);
 
+/* Batches: many independent periodic lattices of one dimension d and one
+   precision (LBM_FP64 or LBM_FP32), each with its own dims, tau, u, R and m4,
+   advanced together.  Instance i takes dims[i*d .. i*d+d-1], tau[i] and
+   params[i] (periodic axes; one stream for all; the allocator of each
+   instance serves its buffers, that of instance 0 the batch tables).
+   lbm_batch_step advances every instance by n steps, one launch per step
+   over a table of (instance, row) tiles, so instances of any size share the
+   chip.  lbm_batch_tune times the block shapes 64x4, 128x2 and 256x1 over
+   trial_steps steps (restoring the states afterwards), keeps the fastest and
+   reports {tx, ty} in config_out[0..1] and its time per step.
+   lbm_batch_instance(b, i) returns the handle of instance i for lbm_moments,
+   lbm_info and the state calls; lbm_step on it is rejected.
+   lbm_batch_set_initial takes the instances' phi0 concatenated in instance
+   order (and their gradients, d planes per instance, or NULL for finite
+   differences).  lbm_batch_moments fills count x LBM_NSCALARS scalars (see
+   lbm_moments).  Errors as for the single-lattice calls, plus
+   LBM_EUNSUPPORTED for walls or the split mode; messages through
+   lbm_batch_last_error (NULL batch: failures of lbm_batch_create). */
+typedef struct lbm_batch lbm_batch;
+int lbm_batch_create(int count, int d, const int64_t* dims, const double* tau,
+                     const lbm_params* params, lbm_batch** out);
+int lbm_batch_set_initial(lbm_batch* b, const double* phi0_dev, const double* grad_dev);
+int lbm_batch_step(lbm_batch* b, int64_t n);
+int lbm_batch_tune(lbm_batch* b, int trial_steps, int32_t* config_out, double* ms_per_step_out);
+lbm_handle* lbm_batch_instance(const lbm_batch* b, int i);
+int lbm_batch_moments(lbm_batch* b, double* scalars_host);
+const char* lbm_batch_last_error(const lbm_batch* b);
+int lbm_batch_destroy(lbm_batch* b);
+
 const char* lbm_last_error(const lbm_handle* h);
 
 /* Release all device memory of h (through free_fn).  NULL is accepted. */

@@ -6,7 +6,7 @@ The binding is imported lazily so that `paper_2410_13165_amd.inputs` and
 `paper_2410_13165_amd.build` work without the compiled library.
 """
 
-__all__ = ["Lattice", "Field", "LbmError", "load_library", "equilibrium_weights"]
+__all__ = ["Lattice", "Batch", "Field", "LbmError", "load_library", "equilibrium_weights"]
 
 
 def __getattr__(name):

@@ -36,6 +36,7 @@ struct lbm_handle {
   int cur = 0;
   int64_t step = 0;
   bool initialised = false;
+  bool batch_member = false;  // stepped only through its lbm_batch
   std::string err;
   // how the current state was initialised (gradients w.r.t. phi0 need it)
   int init_kind = 0;  // 0 unknown, 1 analytic field, 2 device phi0 + FD gradient,
@@ -451,6 +452,7 @@ int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_ph
 int lbm_step(lbm_handle* h, int64_t n) {
   if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
   if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
+  if (h->batch_member) return fail(h, LBM_EINVAL, "batch instances are stepped by lbm_batch_step");
   if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state (call lbm_set_initial)");
   for (int64_t i = 0; i < n; ++i) {
     const int src = h->cur, dst = 1 - h->cur;
@@ -773,6 +775,280 @@ int lbm_destroy(lbm_handle* h) {
   tape_clear(h);
   release(h);
   delete h;
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct lbm_batch {
+  std::vector<lbm_handle*> inst;
+  int d = 0, precision = 0;
+  hipStream_t stream = nullptr;
+  lbm_handle* owner = nullptr;  // instance 0: its allocator serves the tables
+  KParams* d_kps = nullptr;
+  void** d_bufs = nullptr;
+  BatchTile* d_tiles = nullptr;
+  int max_tiles = 0, ntiles = 0;
+  int tx = 64, ty = 4;
+  int cur = 0;
+  int64_t step = 0;
+  std::string err;
+};
+
+namespace {
+
+int bfail(lbm_batch* b, int code, const std::string& msg) {
+  if (b)
+    b->err = msg;
+  else
+    g_create_error = msg;
+  return code;
+}
+
+int batch_tiles(lbm_batch* b, int tx, int ty) {
+  std::vector<BatchTile> t;
+  for (size_t i = 0; i < b->inst.size(); ++i)
+    for (int r = 0; r < b->inst[i]->kp.rows; r += ty) t.push_back(BatchTile{static_cast<int>(i), r});
+  if (static_cast<int>(t.size()) > b->max_tiles) return bfail(b, LBM_EINVAL, "tile table overflow");
+  hipError_t e = hipMemcpyAsync(b->d_tiles, t.data(), sizeof(BatchTile) * t.size(),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("tile upload: ") + hipGetErrorString(e));
+  b->ntiles = static_cast<int>(t.size());
+  b->tx = tx;
+  b->ty = ty;
+  return LBM_OK;
+}
+
+int batch_upload(lbm_batch* b) {
+  std::vector<KParams> kps(b->inst.size());
+  std::vector<void*> bufs(2 * b->inst.size());
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    kps[i] = b->inst[i]->kp;
+    bufs[2 * i] = b->inst[i]->buf[0];
+    bufs[2 * i + 1] = b->inst[i]->buf[1];
+  }
+  hipError_t e = hipMemcpyAsync(b->d_kps, kps.data(), sizeof(KParams) * kps.size(),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_bufs, bufs.data(), sizeof(void*) * bufs.size(), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int batch_run(lbm_batch* b, int64_t n) {
+  if (n <= 0) return LBM_OK;
+  for (int64_t done = 0; done < n;) {
+    const int chunk = static_cast<int>(std::min<int64_t>(n - done, 1 << 20));
+    hipError_t e = launch_batch(b->d, b->d_kps, b->d_bufs, b->d_tiles, b->ntiles, b->tx, b->ty,
+                                b->precision, b->cur, chunk, b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
+    b->cur = (b->cur + chunk) & 1;
+    done += chunk;
+  }
+  b->step += n;
+  for (lbm_handle* h : b->inst) {
+    h->cur = b->cur;
+    h->step = b->step;
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(int count, int d, const int64_t* dims, const double* tau,
+                     const lbm_params* params, lbm_batch** out) {
+  if (out) *out = nullptr;
+  if (!out || !dims || !tau || !params || count < 1)
+    return bfail(nullptr, LBM_EINVAL, "null argument or count < 1");
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return bfail(nullptr, LBM_ENOMEM, "host allocation failed");
+  b->d = d;
+  b->precision = params[0].precision;
+  b->stream = static_cast<hipStream_t>(params[0].stream);
+  auto abort_create = [&](int rc) {
+    std::string msg = g_create_error;
+    for (lbm_handle* h : b->inst) lbm_destroy(h);
+    if (b->owner) {
+      dev_free(b->owner, b->d_kps);
+      dev_free(b->owner, b->d_bufs);
+      dev_free(b->owner, b->d_tiles);
+    }
+    delete b;
+    g_create_error = msg;
+    return rc;
+  };
+  int64_t total_rows = 0;
+  for (int i = 0; i < count; ++i) {
+    if (params[i].precision != b->precision || params[i].stream != params[0].stream)
+      return abort_create(bfail(nullptr, LBM_EINVAL, "batch instances need one precision and one stream"));
+    if (params[i].precision == LBM_FP32_SPLIT)
+      return abort_create(bfail(nullptr, LBM_EUNSUPPORTED, "batches support LBM_FP64 and LBM_FP32"));
+    for (int a = 0; a < d; ++a)
+      if (params[i].bc[a] != LBM_BC_PERIODIC)
+        return abort_create(bfail(nullptr, LBM_EUNSUPPORTED, "batch instances must be periodic"));
+    lbm_handle* h = nullptr;
+    int rc = lbm_create(d, dims + static_cast<size_t>(i) * d, tau[i], &params[i], &h);
+    if (rc != LBM_OK) return abort_create(rc);
+    h->batch_member = true;
+    b->inst.push_back(h);
+    total_rows += h->kp.rows;
+  }
+  b->owner = b->inst[0];
+  if (total_rows > std::numeric_limits<int32_t>::max())
+    return abort_create(bfail(nullptr, LBM_EINVAL, "too many rows in the batch"));
+  b->max_tiles = static_cast<int>(total_rows);
+  b->d_kps = static_cast<KParams*>(dev_alloc(b->owner, sizeof(KParams) * count));
+  b->d_bufs = static_cast<void**>(dev_alloc(b->owner, sizeof(void*) * 2 * count));
+  b->d_tiles = static_cast<BatchTile*>(dev_alloc(b->owner, sizeof(BatchTile) * b->max_tiles));
+  if (!b->d_kps || !b->d_bufs || !b->d_tiles)
+    return abort_create(bfail(nullptr, LBM_ENOMEM, "batch tables"));
+  int rc = batch_upload(b);
+  if (rc == LBM_OK) rc = batch_tiles(b, 64, 4);
+  if (rc != LBM_OK) {
+    g_create_error = b->err;
+    return abort_create(rc);
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_set_initial(lbm_batch* b, const double* phi0_dev, const double* grad_dev) {
+  if (!b || !phi0_dev) return bfail(b, LBM_EINVAL, "null argument");
+  int64_t off = 0;
+  for (lbm_handle* h : b->inst) {
+    int rc = lbm_set_initial(h, phi0_dev + off, grad_dev ? grad_dev + off * b->d : nullptr);
+    if (rc != LBM_OK) return bfail(b, rc, h->err);
+    off += h->nodes;
+  }
+  b->cur = 0;
+  b->step = 0;
+  return batch_upload(b);  // float32 references may have changed
+}
+
+int lbm_batch_step(lbm_batch* b, int64_t n) {
+  if (!b) return bfail(nullptr, LBM_EINVAL, "null batch");
+  if (n < 0) return bfail(b, LBM_EINVAL, "n must be >= 0");
+  for (lbm_handle* h : b->inst)
+    if (!h->initialised) return bfail(b, LBM_EINVAL, "an instance has no initial state");
+  return batch_run(b, n);
+}
+
+int lbm_batch_tune(lbm_batch* b, int trial_steps, int32_t* config_out, double* ms_per_step_out) {
+  if (!b) return bfail(nullptr, LBM_EINVAL, "null batch");
+  if (trial_steps < 1) return bfail(b, LBM_EINVAL, "trial_steps must be >= 1");
+  for (lbm_handle* h : b->inst)
+    if (!h->initialised) return bfail(b, LBM_EINVAL, "an instance has no initial state");
+  // keep the states: trials advance the lattices
+  std::vector<void*> saved;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(b->stream);
+    for (size_t i = 0; i < saved.size(); ++i) dev_free(b->inst[i], saved[i]);
+  };
+  for (lbm_handle* h : b->inst) {
+    void* s = dev_alloc(h, state_bytes(h));
+    if (!s) {
+      cleanup();
+      return bfail(b, LBM_ENOMEM, "tuning buffers");
+    }
+    saved.push_back(s);
+    if (copy_state_out(h, s) != hipSuccess) {
+      cleanup();
+      return bfail(b, LBM_EDEVICE, "tuning state copy");
+    }
+  }
+  const int cur0 = b->cur;
+  const int64_t step0 = b->step;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return bfail(b, LBM_EDEVICE, "hipEventCreate");
+  }
+  struct Cand {
+    int tx, ty;
+  };
+  const Cand cands[] = {{64, 4}, {128, 2}, {256, 1}};
+  double best = 1e300;
+  Cand pick = cands[0];
+  int rc = LBM_OK;
+  for (const Cand& c : cands) {
+    rc = batch_tiles(b, c.tx, c.ty);
+    if (rc != LBM_OK) break;
+    rc = batch_run(b, 1);  // warm-up
+    if (rc != LBM_OK) break;
+    (void)hipEventRecord(e0, b->stream);
+    rc = batch_run(b, trial_steps);
+    (void)hipEventRecord(e1, b->stream);
+    if (rc != LBM_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = bfail(b, LBM_EDEVICE, "tuning run");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double per = ms / trial_steps;
+    if (per < best) {
+      best = per;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // restore the states and the step counters
+  for (size_t i = 0; i < b->inst.size() && rc == LBM_OK; ++i) {
+    lbm_handle* h = b->inst[i];
+    h->cur = cur0;
+    if (lbm_set_state(h, saved[i], step0) != LBM_OK) rc = bfail(b, LBM_EDEVICE, h->err);
+  }
+  b->cur = cur0;
+  b->step = step0;
+  cleanup();
+  if (rc != LBM_OK) return rc;
+  rc = batch_tiles(b, pick.tx, pick.ty);
+  if (rc != LBM_OK) return rc;
+  for (lbm_handle* h : b->inst) h->init_kind = 0;
+  if (config_out) {
+    config_out[0] = pick.tx;
+    config_out[1] = pick.ty;
+  }
+  if (ms_per_step_out) *ms_per_step_out = best;
+  return LBM_OK;
+}
+
+lbm_handle* lbm_batch_instance(const lbm_batch* b, int i) {
+  if (!b || i < 0 || i >= static_cast<int>(b->inst.size())) return nullptr;
+  return b->inst[i];
+}
+
+int lbm_batch_moments(lbm_batch* b, double* scalars_host) {
+  if (!b || !scalars_host) return bfail(b, LBM_EINVAL, "null argument");
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    int rc = lbm_moments(b->inst[i], nullptr, scalars_host + i * LBM_NSCALARS);
+    if (rc != LBM_OK) return bfail(b, rc, b->inst[i]->err);
+  }
+  return LBM_OK;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) {
+  return b ? b->err.c_str() : g_create_error.c_str();
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_OK;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->owner) {
+    dev_free(b->owner, b->d_kps);
+    dev_free(b->owner, b->d_bufs);
+    dev_free(b->owner, b->d_tiles);
+  }
+  for (lbm_handle* h : b->inst) lbm_destroy(h);
+  delete b;
   return LBM_OK;
 }
 

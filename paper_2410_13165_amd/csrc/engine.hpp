@@ -70,6 +70,13 @@ struct KParams {
   FieldDev field;
 };
 
+// One block of a batched launch: rows row0 .. row0 + blockDim.y - 1 of an
+// instance.
+struct BatchTile {
+  int inst;
+  int row0;
+};
+
 struct LaunchShape {
   int tx, ty;
   unsigned blocks;
@@ -99,6 +106,12 @@ hipError_t launch_moments(const KParams& p, int mode, const void* f, const doubl
 // Sum over the nodes of phi0 (analytic when arr == nullptr), into out[0].
 hipError_t launch_sum_phi0(const KParams& p, const double* arr, double* partial,
                            double* out, hipStream_t stream);
+
+// nsteps steps of every instance of a batch (periodic lattices of one d and
+// precision), one launch per step over the tile table.
+hipError_t launch_batch(int d, const KParams* kps, void* const* bufs, const BatchTile* tiles,
+                        int ntiles, int tx, int ty, int mode, int cur, int nsteps,
+                        hipStream_t stream);
 
 // Adjoint step lambda^{n+1} -> lambda^n (adjoint.hip).  g: forward state at
 // step n (nullable); when given, per-block partial sums of

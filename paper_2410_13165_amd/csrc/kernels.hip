@@ -451,11 +451,9 @@ __device__ __forceinline__ void collide_store(T (&f)[q_of(D)], T* __restrict__ d
 // base address, so the common path keeps its registers); the half-way scheme
 // then subtracts the node's own post-collision kbar value.
 template <int D, class T>
-__global__ void __launch_bounds__(256)
-    k_step(const T* __restrict__ src, T* __restrict__ dst, const KParams p) {
+__device__ __forceinline__ void step_row(const T* __restrict__ src, T* __restrict__ dst,
+                                         const KParams& p, int row) {
   constexpr int Q = q_of(D);
-  const int row = blockIdx.x * blockDim.y + threadIdx.y;
-  if (row >= p.rows) return;
   RowInfo<D> r;
   row_setup<D>(p, row, r);
   if (r.rowwall) return;
@@ -486,6 +484,29 @@ __global__ void __launch_bounds__(256)
     }
     collide_store<D, T>(f, dst, ps, node, p);
   }
+}
+
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_step(const T* __restrict__ src, T* __restrict__ dst, const KParams p) {
+  const int row = blockIdx.x * blockDim.y + threadIdx.y;
+  if (row >= p.rows) return;
+  step_row<D, T>(src, dst, p, row);
+}
+
+// Many lattices in one launch (periodic instances): block b updates rows
+// tiles[b].row0 .. + blockDim.y - 1 of instance tiles[b].inst, whose parameter
+// block is kps[inst] and whose two state buffers are bufs[2 inst], bufs[2 inst + 1]
+// (cur selects the source).
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_step_batch(const KParams* __restrict__ kps, T* const* __restrict__ bufs,
+                 const BatchTile* __restrict__ tiles, const int cur) {
+  const BatchTile t = tiles[blockIdx.x];
+  const KParams& p = kps[t.inst];
+  const int row = t.row0 + threadIdx.y;
+  if (row >= p.rows) return;
+  step_row<D, T>(bufs[2 * t.inst + cur], bufs[2 * t.inst + 1 - cur], p, row);
 }
 
 // Split representation: phi (float64) and g_k = f_k - omega_k phi (float32),
@@ -1013,6 +1034,37 @@ hipError_t launch_sum_phi0(const KParams& p, const double* arr, double* partial,
     case 2: return sum_phi0_d<2>(p, arr, partial, out, stream);
     case 3: return sum_phi0_d<3>(p, arr, partial, out, stream);
     case 4: return sum_phi0_d<4>(p, arr, partial, out, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int D>
+static hipError_t batch_d(const KParams* kps, void* const* bufs, const BatchTile* tiles,
+                          int ntiles, int tx, int ty, int mode, int cur, int nsteps,
+                          hipStream_t stream) {
+  const dim3 block(tx, ty);
+  for (int s = 0; s < nsteps; ++s) {
+    const int c = (cur + s) & 1;
+    if (mode == kFP64)
+      hipLaunchKernelGGL((k_step_batch<D, double>), dim3(ntiles), block, 0, stream, kps,
+                         reinterpret_cast<double* const*>(bufs), tiles, c);
+    else
+      hipLaunchKernelGGL((k_step_batch<D, float>), dim3(ntiles), block, 0, stream, kps,
+                         reinterpret_cast<float* const*>(bufs), tiles, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_batch(int d, const KParams* kps, void* const* bufs, const BatchTile* tiles,
+                        int ntiles, int tx, int ty, int mode, int cur, int nsteps,
+                        hipStream_t stream) {
+  switch (d) {
+    case 1: return batch_d<1>(kps, bufs, tiles, ntiles, tx, ty, mode, cur, nsteps, stream);
+    case 2: return batch_d<2>(kps, bufs, tiles, ntiles, tx, ty, mode, cur, nsteps, stream);
+    case 3: return batch_d<3>(kps, bufs, tiles, ntiles, tx, ty, mode, cur, nsteps, stream);
+    case 4: return batch_d<4>(kps, bufs, tiles, ntiles, tx, ty, mode, cur, nsteps, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -98,6 +98,31 @@ ADJOINT_D3Q19 = {"d": 3, "n": 256, "u": [0.05, 0.1, 0.08], "steps": 1000, "every
                  "seed_init": 5, "seed_target": 6, "corr": 0.1}
 
 
+# Stability sweep: 512 independent periodic D2Q9 lattices, sizes drawn from
+# {64^2, 128^2, 256^2, 512^2}, tau ~ U(0.5, 2.0), sigma ~ U(-0.75, 0.75)^2
+# (straddling the |sigma| < 1/2 region), R = 0, K = 1, noise N(0, 1e-6), 4000 steps.
+SWEEP_D2Q9 = {"count": 512, "sizes": [64, 128, 256, 512], "tau": (0.5, 2.0),
+              "sigma": (-0.75, 0.75), "std": 1e-3, "steps": 4000, "seed": 4}
+
+
+def sweep_specs(count=None, seed=None):
+    w = SWEEP_D2Q9
+    rng = np.random.default_rng(w["seed"] if seed is None else seed)
+    specs = []
+    for _ in range(count or w["count"]):
+        n = int(w["sizes"][rng.integers(0, len(w["sizes"]))])
+        specs.append({"dims": (n, n), "tau": float(rng.uniform(*w["tau"])),
+                      "u": rng.uniform(*w["sigma"], size=2).tolist(), "dx": 1.0 / n, "K": 1})
+    return specs
+
+
+def sweep_phi0(specs, seed=None):
+    w = SWEEP_D2Q9
+    rng = np.random.default_rng((w["seed"] if seed is None else seed) + 1000)
+    return np.concatenate([rng.normal(0.0, w["std"], size=int(np.prod(sp["dims"])))
+                           for sp in specs])
+
+
 # Workload of the benchmark: D3Q19 on the unit cube, 512 nodes per axis,
 # full-way Dirichlet walls on all six faces with data from four random cosines
 # (seed 3), u = (0.05, 0.1, 0.08) (Table 3), R = 1, K = 3, P = 4.

@@ -85,6 +85,17 @@ SIGNATURES = {
     "lbm_profile_begin": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(C.c_int64)]),
+    "lbm_batch_create": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double), C.POINTER(LbmParams),
+                                   C.POINTER(C.c_void_p)]),
+    "lbm_batch_set_initial": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lbm_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_batch_tune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_double)]),
+    "lbm_batch_instance": (C.c_void_p, [C.c_void_p, C.c_int]),
+    "lbm_batch_moments": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "lbm_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_batch_destroy": (C.c_int, [C.c_void_p]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_destroy": (C.c_int, [C.c_void_p]),
 }
@@ -358,6 +369,145 @@ class Lattice:
             self._closed = True
             self.lib.lbm_destroy(self._h)
             self._h = None
+            self._bufs.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _BatchMember(Lattice):
+    """Read-only view of one instance of a Batch (moments, info, state)."""
+
+    def __init__(self, batch, handle, d, dims, precision, R):
+        self._torch = batch._torch
+        self.lib = batch.lib
+        self.device = batch.device
+        self.d = d
+        self.dims = tuple(dims)
+        self.precision = precision
+        self._h = C.c_void_p(handle)
+        self._closed = True  # owned by the batch
+        self._bufs = {}
+        p = LbmParams()
+        p.R = R
+        self._params = p
+
+    def close(self):
+        pass
+
+
+class Batch:
+    """Independent periodic lattices of one d and precision advanced together.
+
+    specs: list of dicts with keys dims, tau, dx, u and optional R, m4, g.
+    """
+
+    def __init__(self, d: int, specs, precision: str = "fp32", device=None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.d = int(d)
+        self.count = len(specs)
+        self._bufs = {}
+        self._b = None
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            except RuntimeError:
+                return None
+            self._bufs[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(ptr, ctx):
+            self._bufs.pop(ptr, None)
+
+        self._alloc_cb = _ALLOC(_alloc)
+        self._free_cb = _FREE(_free)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        params = (LbmParams * self.count)()
+        dims = (C.c_int64 * (self.count * self.d))()
+        taus = (C.c_double * self.count)()
+        self.specs = [dict(sp) for sp in specs]
+        for i, sp in enumerate(self.specs):
+            p = params[i]
+            self.lib.lbm_params_default(C.byref(p))
+            p.dx = float(sp["dx"])
+            for a in range(self.d):
+                p.u[a] = float(sp["u"][a])
+                dims[i * self.d + a] = int(sp["dims"][a])
+            p.R = float(sp.get("R", 0.0))
+            p.g = float(sp.get("g", 0.5))
+            if sp.get("m4") is not None:
+                p.m4 = float(sp["m4"])
+                p.use_m4 = 1
+            p.init_order = int(sp.get("K", 1))
+            p.precision = PRECISION[precision]
+            p.alloc = self._alloc_cb
+            p.free_fn = self._free_cb
+            p.stream = C.c_void_p(self.stream.cuda_stream)
+            taus[i] = float(sp["tau"])
+        self.precision = precision
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.lbm_batch_create(self.count, self.d, dims, taus, params, C.byref(h))
+        if rc != OK:
+            raise LbmError(rc, self.lib.lbm_batch_last_error(None).decode())
+        self._b = h
+        self._params = params
+        self.nodes = [int(np.prod(sp["dims"])) for sp in self.specs]
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LbmError(rc, self.lib.lbm_batch_last_error(self._b).decode())
+
+    def set_initial(self, phi0_concat, grad_concat=None):
+        torch = self._torch
+        phi = phi0_concat.to(device=self.device, dtype=torch.float64).contiguous()
+        g = None if grad_concat is None else grad_concat.to(device=self.device,
+                                                            dtype=torch.float64).contiguous()
+        self._check(self.lib.lbm_batch_set_initial(
+            self._b, C.c_void_p(phi.data_ptr()), C.c_void_p(g.data_ptr()) if g is not None else None))
+        self._keep = (phi, g)
+        return self
+
+    def step(self, n: int):
+        self._check(self.lib.lbm_batch_step(self._b, int(n)))
+        return self
+
+    def tune(self, trial_steps: int = 10) -> dict:
+        cfg = (C.c_int32 * 2)()
+        ms = C.c_double()
+        self._check(self.lib.lbm_batch_tune(self._b, int(trial_steps), cfg, C.byref(ms)))
+        return {"tx": cfg[0], "ty": cfg[1], "ms_per_step": ms.value}
+
+    def moments(self) -> np.ndarray:
+        out = (C.c_double * (NSCALARS * self.count))()
+        self._check(self.lib.lbm_batch_moments(self._b, out))
+        return np.array(out[:]).reshape(self.count, NSCALARS)
+
+    def instance(self, i: int) -> Lattice:
+        h = self.lib.lbm_batch_instance(self._b, int(i))
+        if not h:
+            raise IndexError(i)
+        sp = self.specs[i]
+        return _BatchMember(self, h, self.d, sp["dims"], self.precision, float(sp.get("R", 0.0)))
+
+    def close(self):
+        if self._b is not None:
+            self.lib.lbm_batch_destroy(self._b)
+            self._b = None
             self._bufs.clear()
 
     def __enter__(self):

@@ -1,0 +1,121 @@
+"""Batched lattices (one launch per step over all instances) against
+per-instance oracle runs, and the stability sweep against the oracle's
+brute-force spectral radius of the amplification matrix."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import lbm_oracle as O
+from paper_2410_13165_amd import inputs
+from tests.pairs import oracle_problem, rel_l2, to_oracle_order
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _specs(rng, count, sizes, tau_range, sig_range, d=2):
+    specs = []
+    for i in range(count):
+        n = sizes[rng.integers(0, len(sizes))]
+        dims = (n + int(rng.integers(0, 7)), n - int(rng.integers(0, 5)))[:d]
+        specs.append({"dims": dims, "tau": float(rng.uniform(*tau_range)),
+                      "u": rng.uniform(*sig_range, size=d).tolist(), "dx": 1.0 / dims[0]})
+    return specs
+
+
+def _concat_phi0(specs, seed):
+    parts = [inputs.noise(tuple(reversed(sp["dims"])), seed + i, std=1e-3).ravel()
+             for i, sp in enumerate(specs)]
+    return parts, torch.from_numpy(np.concatenate(parts))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+@pytest.mark.parametrize("K", [1, 3])
+def test_batch_matches_oracle_per_instance(precision, tol, K):
+    from paper_2410_13165_amd import Batch
+    rng = np.random.default_rng(40 + K)
+    specs = _specs(rng, 7, [16, 24, 40], (0.5, 1.4), (-0.45, 0.45))
+    for sp in specs:
+        sp["K"] = K
+    parts, phi0 = _concat_phi0(specs, 500)
+    steps = 25
+    with Batch(2, specs, precision=precision) as b:
+        b.set_initial(phi0)
+        b.step(steps)
+        for i, sp in enumerate(specs):
+            prob = oracle_problem(2, sp["dims"], sp["dx"], None, u=sp["u"], tau=sp["tau"], K=K)
+            run = O.Run(prob, phi0=to_oracle_order(parts[i].reshape(tuple(reversed(sp["dims"])))))
+            run.step(steps)
+            got = to_oracle_order(b.instance(i).phi().cpu().numpy())
+            assert rel_l2(got, run.phi()) <= tol, (i, sp)
+
+
+def test_tuner_restores_state_and_configs_agree():
+    """Every block shape gives bitwise identical states; tuning leaves the
+    state where it was."""
+    from paper_2410_13165_amd import Batch
+    rng = np.random.default_rng(44)
+    specs = _specs(rng, 9, [32, 64, 100], (0.5, 1.2), (-0.4, 0.4))
+    parts, phi0 = _concat_phi0(specs, 700)
+    with Batch(2, specs, precision="fp32") as a, Batch(2, specs, precision="fp32") as b:
+        a.set_initial(phi0)
+        b.set_initial(phi0)
+        a.step(3)
+        b.step(3)
+        before = [b.instance(i).phi().clone() for i in range(len(specs))]
+        cfg = b.tune(5)
+        print("[batch] tuned", cfg, flush=True)
+        for i in range(len(specs)):
+            assert torch.equal(before[i], b.instance(i).phi())
+        assert b.instance(0).info()["step"] == 3
+        a.step(40)
+        b.step(40)
+        for i in range(len(specs)):
+            assert torch.equal(a.instance(i).phi(), b.instance(i).phi()), i
+
+
+def test_batch_rejects_stepping_an_instance():
+    from paper_2410_13165_amd import Batch, LbmError
+    specs = [{"dims": (16, 16), "tau": 0.5, "u": [0.1, 0.1], "dx": 1 / 16}]
+    with Batch(2, specs, precision="fp64") as b:
+        b.set_initial(torch.zeros(256, dtype=torch.float64))
+        with pytest.raises(LbmError, match="batch"):
+            b.instance(0).step(1)
+
+
+def _rho(u, s, m=24):
+    xs = np.linspace(0, 2 * np.pi, m, endpoint=False)
+    return max(np.max(np.abs(np.linalg.eigvals(O.amplification_matrix(u, xi, s=s))))
+               for xi in itertools.product(xs, repeat=len(u)))
+
+
+def test_stability_sweep_matches_spectral_radius():
+    """Instances with rho(G) > 1 (brute force over the wave numbers, any s) grow,
+    the others do not; at s = 2 the region is the entropy region min omega > 0."""
+    from paper_2410_13165_amd import Batch
+    rng = np.random.default_rng(4)
+    specs = _specs(rng, 24, [32], (0.5, 2.0), (-0.75, 0.75))
+    # make a third of them s = 2 so that the entropy criterion applies
+    for sp in specs[:8]:
+        sp["tau"] = 0.5
+    parts, phi0 = _concat_phi0(specs, 900)
+    steps = 400
+    with Batch(2, specs, precision="fp64") as b:
+        b.set_initial(phi0)
+        m0 = b.moments()
+        b.step(steps)
+        m1 = b.moments()
+        infos = [b.instance(i).info() for i in range(len(specs))]
+    growth = np.sqrt(m1[:, 1] / m0[:, 1])
+    for i, sp in enumerate(specs):
+        rho = _rho(sp["u"], 1.0 / sp["tau"])
+        print(f"[sweep] u={np.round(sp['u'], 3)} tau={sp['tau']:.3f} rho={rho:.6f} "
+              f"min_omega={infos[i]['min_omega']:.4f} growth={growth[i]:.3e}", flush=True)
+        if rho > 1.02:
+            assert growth[i] > 2.0, (i, rho, growth[i])
+        elif rho < 1 + 1e-9:
+            assert growth[i] < 1.2, (i, rho, growth[i])
+        if sp["tau"] == 0.5 and abs(infos[i]["min_omega"]) > 1e-2:
+            assert (infos[i]["min_omega"] > 0) == (rho < 1 + 1e-9), (i, rho)
