@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -160,6 +161,49 @@ def run_adjoint(precision: str = "fp32", n=None, steps=None):
     }
 
 
+def run_fixed_error(target=1e-6, sizes=(64, 96, 128, 192, 256, 384, 512)):
+    """Smallest grid of the benchmark family (D3Q19 full-way, same field, final
+    time t = 2000/511) whose RMSE relative to the RMS of phi reaches `target`,
+    per storage mode, and the time to solution there (one timed run per size,
+    no warm-up, so the small sizes include launch overhead)."""
+    import torch
+    from paper_2410_13165_amd import Lattice, inputs
+    w = inputs.BENCH_D3Q19
+    T = w["steps"] / (w["n"] - 1)
+    spec = inputs.bench_field()
+    out = {}
+    for mode in ("fp64", "fp32_split", "fp32"):
+        tried = []
+        hit = None
+        for n in sizes:
+            steps = int(round(T * (n - 1)))
+            lat = Lattice(3, (n, n, n), 0.5, dx=1.0 / (n - 1), u=w["u"], R=w["R"],
+                          bc=["fullway"] * 3, precision=mode, field=spec)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lat.step(steps)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                dg = lat.diagnostics()
+            finally:
+                lat.close()
+                torch.cuda.empty_cache()
+            rmse = dg["rmse"]
+            rel = rmse / math.sqrt(dg["sum_phi2"] / n ** 3)
+            rec = {"n": n, "steps": steps, "rmse": float(f"{rmse:.4g}"),
+                   "rel_rmse": float(f"{rel:.4g}"), "seconds": round(sec, 4),
+                   "mlups": round(n ** 3 * steps / sec / 1e6, 1)}
+            tried.append(rec)
+            print(f"# fixed error {mode}: n={n} rmse={rmse:.3e} relative {rel:.3e} {sec:.3f} s",
+                  file=sys.stderr, flush=True)
+            if rel <= target:
+                hit = rec
+                break
+        out[mode] = {"reached": hit, "runs": tried}
+    return {"target_rmse": target, "t_final": T, "modes": out}
+
+
 def run_sweep(steps=None, count=None, precision="fp32"):
     """512 independent D2Q9 lattices advanced together (tuned launch form);
     per-instance growth of the L2 norm of phi."""
@@ -242,6 +286,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-fixed-error", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args(argv)
@@ -276,6 +321,9 @@ def main(argv=None):
         print(f"# {m}: {results[m]['mlups']:.0f} MLUPS, bulk {results[m]['bulk_gbs']:.0f} GB/s, "
               f"rmse {results[m]['rmse']:.3e}", file=sys.stderr, flush=True)
     head = results[modes[0]]
+    fixed = None
+    if not args.no_fixed_error:
+        fixed = run_fixed_error()
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep()
@@ -331,6 +379,7 @@ def main(argv=None):
         "modes": {m: {k: (float(f"{v:.6g}") if isinstance(v, float) else v)
                       for k, v in r.items()}
                   for m, r in results.items()},
+        "fixed_error": fixed,
         "sweep": sweep,
         "adjoint_fwd_ratio": round(adj["ratio"], 4) if adj else None,
         "adjoint": ({k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in adj.items()}
