@@ -243,6 +243,30 @@ int lbm_tape_end(lbm_handle* h);
 int lbm_equilibrium_weights(int d, const double* u, double g, int use_m4, double m4,
                             double* omega_out, double* m4_out, double* min_omega_out);
 
+/* Stability maps (Sec. 4): for each of `count` parameter points, the
+   spectral radius of the amplification matrix of eq. (G) over the wave-number
+   grid xi = 2 pi j / m, j in {0..m-1}^d, and the smallest equilibrium weight.
+   The matrix is taken for a general relaxation rate s, G(xi) =
+   T(xi) [(1 - s) I + s omega 1^T] with T(xi) = diag(exp(-i c_k . xi)) (the
+   streaming symbol with the imaginary unit the printed form omits); s = 2 is
+   eq. (G).  Point pt has sigma = sigma_dev[pt*d .. pt*d+d) (c = 1, so
+   sigma = u) and s = s_dev[pt]; omega comes from eq. (omega_k-2) with m4 from
+   eq. (meq-4rd) at weight g (NaN = 1/2).  Outputs, all device arrays of
+   `count` entries: rho_dev[pt] = max over the grid of rho(G(xi));
+   min_omega_dev[pt] = min_k omega_k (nullable; entropy stability, Prop. 1,
+   holds iff it is > 0); unconverged_dev[pt] = the number of grid points whose
+   eigenvalue iteration did not settle (nullable; 0 in every tested case).
+   The paper's L^2 stability at s = 2 is rho = 1; rho > 1 means growth.
+   All pointers are device memory borrowed for the call; the work is queued on
+   `stream` (a hipStream_t, NULL = default stream) and the call returns without
+   synchronising.  Errors (reported by lbm_last_error(NULL)): LBM_EINVAL for d
+   outside 1..4, count < 0 or > 2^31 - 1, m outside 1..2^20, m^d > 2^31,
+   non-finite g, or null sigma_dev / s_dev / rho_dev with count > 0;
+   LBM_EDEVICE for a failed launch. */
+int lbm_stability_map(int d, int64_t count, const double* sigma_dev, const double* s_dev,
+                      double g, int32_t m, double* rho_dev, double* min_omega_dev,
+                      int32_t* unconverged_dev, void* stream);
+
 /* Batches: many independent periodic lattices of one dimension d and one
    precision (LBM_FP64 or LBM_FP32), each with its own dims, tau, u, R and m4,
    advanced together.  Instance i takes dims[i*d .. i*d+d-1], tau[i] and

@@ -50,7 +50,7 @@ import numpy as np
 __all__ = [
     "velocity_set", "opposite", "moment_matrix", "m4_interpolated", "epsilon",
     "omega", "min_omega", "ExactField", "Problem", "Run", "amplification_matrix",
-    "fd4_gradient", "rmse",
+    "spectral_radius_grid", "fd4_gradient", "rmse",
 ]
 
 
@@ -575,3 +575,15 @@ def amplification_matrix(u: Sequence[float], xi: Sequence[float], s: float = 2.0
     T = np.diag(np.exp(-1j * (c @ np.asarray(xi, dtype=np.float64))))
     coll = (1.0 - s) * np.eye(q) + s * np.outer(eps, e1)
     return M @ T @ np.linalg.inv(M) @ coll
+
+
+def spectral_radius_grid(u: Sequence[float], s: float, m: int, g: float = 0.5) -> float:
+    """max over the grid xi = 2 pi j / m, j in {0..m-1}^d, of the spectral
+    radius of G(xi) (Sec. 4.2), by dense eigenvalues of each matrix."""
+    u = np.asarray(u, dtype=np.float64)
+    best = 0.0
+    for j in itertools.product(range(m), repeat=u.size):
+        xi = 2.0 * np.pi * np.asarray(j, dtype=np.float64) / m
+        G = amplification_matrix(u, xi, s=s, g=g)
+        best = max(best, float(np.max(np.abs(np.linalg.eigvals(G)))))
+    return best

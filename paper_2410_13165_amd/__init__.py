@@ -6,7 +6,8 @@ The binding is imported lazily so that `paper_2410_13165_amd.inputs` and
 `paper_2410_13165_amd.build` work without the compiled library.
 """
 
-__all__ = ["Lattice", "Batch", "Field", "LbmError", "load_library", "equilibrium_weights"]
+__all__ = ["Lattice", "Batch", "Field", "LbmError", "load_library", "equilibrium_weights",
+           "stability_map"]
 
 
 def __getattr__(name):

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "capi.hip"]
+SOURCES = ["kernels.hip", "adjoint.hip", "stability.hip", "capi.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -764,6 +764,28 @@ int lbm_equilibrium_weights(int d, const double* u, double g, int use_m4, double
   return LBM_OK;
 }
 
+int lbm_stability_map(int d, int64_t count, const double* sigma_dev, const double* s_dev,
+                      double g, int32_t m, double* rho_dev, double* min_omega_dev,
+                      int32_t* unconverged_dev, void* stream) {
+  if (d < 1 || d > kMaxDim) return fail(nullptr, LBM_EINVAL, "d must be in 1..4");
+  if (count < 0 || count > INT32_MAX) return fail(nullptr, LBM_EINVAL, "count out of range");
+  if (m < 1 || m > (1 << 20)) return fail(nullptr, LBM_EINVAL, "m must be in 1..2^20");
+  long long nxi = 1;
+  for (int a = 0; a < d; ++a) {
+    nxi *= m;
+    if (nxi > (1LL << 31)) return fail(nullptr, LBM_EINVAL, "m^d must be <= 2^31");
+  }
+  if (std::isnan(g)) g = 0.5;
+  if (!std::isfinite(g)) return fail(nullptr, LBM_EINVAL, "g must be finite");
+  if (count == 0) return LBM_OK;
+  if (!sigma_dev || !s_dev || !rho_dev)
+    return fail(nullptr, LBM_EINVAL, "sigma, s and rho must not be null");
+  hipError_t e = launch_stability(d, count, sigma_dev, s_dev, g, m, nxi, rho_dev, min_omega_dev,
+                                  unconverged_dev, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "stability kernel");
+  return LBM_OK;
+}
+
 const char* lbm_last_error(const lbm_handle* h) {
   return h ? h->err.c_str() : g_create_error.c_str();
 }

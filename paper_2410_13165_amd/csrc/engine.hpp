@@ -130,4 +130,12 @@ hipError_t launch_adjoint_init(const KParams& p, int mode, const void* lam, cons
 hipError_t launch_sum_partials(const double* partial, long long n, double* out,
                                hipStream_t stream);
 
+// Spectral radius of the amplification matrix over the wave-number grid
+// xi = 2 pi j / m, j in [0, m)^d (nxi = m^d points), for count parameter
+// points (sigma[pt*d .. pt*d+d), s[pt]); one block per point
+// (stability.hip).  min_omega and unconverged are nullable.
+hipError_t launch_stability(int d, long long count, const double* sigma, const double* s,
+                            double g, int m, long long nxi, double* rho, double* min_omega,
+                            int32_t* unconverged, hipStream_t stream);
+
 }  // namespace lbm

@@ -8,6 +8,8 @@
 // every pair (Remark 5), m4 from eq. (meq-4rd).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cmath>
 #include <cstdint>
 
@@ -55,7 +57,7 @@ constexpr int opp_index(int D, int k) {
 }
 
 // Fourth-order moment, eq. (meq-4rd), sigma = u; defined for d >= 2.
-inline double m4_interpolated(int d, const double* u, double g) {
+__host__ __device__ inline double m4_interpolated(int d, const double* u, double g) {
   double s2 = 0.0;
   for (int i = 0; i < d; ++i) s2 += u[i] * u[i];
   double lo = (-6.0 + 2.0 * d + 4.0 * s2) / (3.0 * d * (d - 1));
@@ -72,7 +74,8 @@ inline double m4_interpolated(int d, const double* u, double g) {
 }
 
 // EDF weights, closed form eq. (omega_k-2) with c = 1 and equal m4.
-inline void omega_closed_form(int d, const double* u, double m4, double* w) {
+__host__ __device__ inline void omega_closed_form(int d, const double* u, double m4,
+                                                     double* w) {
   double s2 = 0.0;
   for (int i = 0; i < d; ++i) s2 += u[i] * u[i];
   const int npairs = d * (d - 1) / 2;

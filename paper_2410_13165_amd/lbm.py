@@ -96,6 +96,8 @@ SIGNATURES = {
     "lbm_batch_moments": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "lbm_batch_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_batch_destroy": (C.c_int, [C.c_void_p]),
+    "lbm_stability_map": (C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_double,
+                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_destroy": (C.c_int, [C.c_void_p]),
 }
@@ -135,6 +137,40 @@ def equilibrium_weights(u: Sequence[float], g: float = 0.5, m4: Optional[float] 
     if rc != OK:
         raise LbmError(rc, lib.lbm_last_error(None).decode())
     return np.array(om[: 2 * d * d + 1]), m4o.value, mn.value
+
+
+def stability_map(sigma, s, m: int = 32, g: float = 0.5, device: str = "cuda"):
+    """Spectral radius of the amplification matrix over the grid xi = 2 pi j / m
+    and the smallest equilibrium weight, for a batch of parameter points.
+
+    sigma: (count, d) array of u values; s: (count,) relaxation rates (or a
+    scalar).  Returns a dict of float64/int32 device tensors rho, min_omega,
+    unconverged.  All work runs in the library's stability kernel.
+    """
+    import torch
+    lib = load_library()
+    sig = torch.as_tensor(sigma, dtype=torch.float64)
+    if sig.dim() != 2:
+        raise ValueError("sigma must be (count, d)")
+    count, d = sig.shape
+    ss = torch.as_tensor(s, dtype=torch.float64)
+    if ss.dim() == 0:
+        ss = ss.expand(count)
+    if ss.shape != (count,):
+        raise ValueError("s must be a scalar or have one entry per point")
+    sig = sig.to(device).contiguous()
+    ss = ss.to(device).contiguous()
+    rho = torch.empty(count, dtype=torch.float64, device=device)
+    mw = torch.empty(count, dtype=torch.float64, device=device)
+    unc = torch.empty(count, dtype=torch.int32, device=device)
+    stream = torch.cuda.current_stream(sig.device).cuda_stream
+    rc = lib.lbm_stability_map(int(d), int(count), C.c_void_p(sig.data_ptr()),
+                               C.c_void_p(ss.data_ptr()), float(g), int(m),
+                               C.c_void_p(rho.data_ptr()), C.c_void_p(mw.data_ptr()),
+                               C.c_void_p(unc.data_ptr()), C.c_void_p(stream))
+    if rc != OK:
+        raise LbmError(rc, lib.lbm_last_error(None).decode())
+    return {"rho": rho, "min_omega": mw, "unconverged": unc}
 
 
 class LbmError(RuntimeError):

@@ -162,3 +162,24 @@ def test_host_weights_match_oracle(d):
 def test_host_weights_reject_bad_dimension():
     with pytest.raises(B.LbmError):
         B.equilibrium_weights([0.1] * 5)
+
+
+def test_stability_map_rejects_bad_arguments_before_any_launch():
+    lib = B.load_library()
+    z = None
+    cases = [
+        ((0, 1, z, z, 0.5, 8), "d must be"),
+        ((5, 1, z, z, 0.5, 8), "d must be"),
+        ((2, -1, z, z, 0.5, 8), "count"),
+        ((2, 1, z, z, 0.5, 0), "m must be"),
+        ((2, 1, z, z, 0.5, (1 << 20) + 1), "m must be"),
+        ((4, 1, z, z, 0.5, 1024), "m\\^d"),
+        ((2, 1, z, z, math.inf, 8), "g must be"),
+        ((2, 3, z, z, 0.5, 8), "must not be null"),
+    ]
+    for (d, count, sig, s, g, m), msg in cases:
+        rc = lib.lbm_stability_map(d, count, sig, s, g, m, None, None, None, None)
+        assert rc == B.EINVAL
+        assert re.search(msg, lib.lbm_last_error(None).decode())
+    # nothing to do: success without touching a device
+    assert lib.lbm_stability_map(2, 0, None, None, 0.5, 8, None, None, None, None) == B.OK

@@ -337,6 +337,27 @@ def test_unstable_parameters_have_growing_modes():
     assert rho([0.55]) > 1.05
 
 
+def test_spectral_radius_grid_pins():
+    """The grid maximum of rho(G): xi = 0 alone gives the eigenvalues 1 and
+    1 - s (eq. G-3 at s = 2); at s = 1 the collision is the rank-one projection
+    omega 1^T, so rho(G(xi)) = |sum_k omega_k exp(-i c_k . xi)|; in 1D the
+    region is |sigma| <= 1/2 (Sec. 4.2 and Appendix D)."""
+    for s in (0.5, 1.0, 1.7, 2.0):
+        assert abs(O.spectral_radius_grid([0.2, -0.1], s, 1) - max(1.0, abs(1 - s))) < 1e-12
+    rng = np.random.default_rng(12)
+    for d in (1, 2, 3):
+        u = rng.uniform(-0.4, 0.4, d)
+        c = O.velocity_set(d)
+        w = O.omega(u)
+        m = 6
+        want = max(abs(np.sum(w * np.exp(-2j * np.pi * (c @ np.array(j)) / m)))
+                   for j in itertools.product(range(m), repeat=d))
+        assert abs(O.spectral_radius_grid(u, 1.0, m) - want) < 1e-12
+    assert abs(O.spectral_radius_grid([0.5], 2.0, 64) - 1) < 1e-9
+    assert abs(O.spectral_radius_grid([-0.3], 2.0, 64) - 1) < 1e-12
+    assert O.spectral_radius_grid([0.52], 2.0, 64) > 1.01
+
+
 # ------------------------------------------------------------------- jets ---
 
 def _fd_derivative(fn, h, order):
