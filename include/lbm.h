@@ -91,6 +91,18 @@ typedef enum {
                                 Example 2; periodic lattices only                        */
 } lbm_field_kind;
 
+/* Which derivatives of the Dirichlet data the wall schemes may use. */
+typedef enum {
+  LBM_WALL_JETS = 0,        /* every time/space derivative of the exact solution    */
+  LBM_WALL_TANGENTIAL = 1   /* only h = phi* on the wall: its time and tangential
+                               derivatives; the normal derivatives follow from the
+                               equation (Remark 1, with the division by u_j that the
+                               printed form omits).  Needs u_j != 0 on every
+                               Dirichlet axis j.  A population entering through
+                               several walls (edges, corners) uses the data of the
+                               lowest such axis.                                     */
+} lbm_wall_data;
+
 typedef struct {
   int32_t kind;                 /* lbm_field_kind                                   */
   int32_t n_modes;              /* 1..LBM_MAX_MODES for the sums, ignored otherwise  */
@@ -121,6 +133,7 @@ typedef struct {
   void (*free_fn)(void* ptr, void* ctx);     /* matching free, NULL = hipFree       */
   void* alloc_ctx;
   void* stream;                 /* hipStream_t used for all work, borrowed            */
+  int32_t wall_data;            /* lbm_wall_data; default LBM_WALL_JETS               */
 } lbm_params;
 
 typedef struct {
@@ -141,7 +154,8 @@ typedef struct {
 } lbm_info_t;
 
 /* Fill p with defaults: dx = 1, origin 0, u 0, R 0, g = 1/2, all axes periodic,
-   P = 4, K = 3, LBM_FP64, no field, hipMalloc/hipFree, null stream. */
+   P = 4, K = 3, LBM_FP64, no field, hipMalloc/hipFree, null stream,
+   LBM_WALL_JETS. */
 void lbm_params_default(lbm_params* p);
 
 /* Create a lattice with d in 1..4 axes of dims[0..d-1] nodes and relaxation time

@@ -313,6 +313,11 @@ class Problem:
     m4: Optional[float] = None
     field: Optional[ExactField] = None
     shift: Optional[Sequence[float]] = None  # node offset per axis, in units of dx
+    # "jets": the wall schemes take every derivative from the exact solution;
+    # "tangential": only the Dirichlet data h on the wall are used (its time
+    # and tangential derivatives), normal derivatives follow from the equation
+    # (Remark 1, with the division by u_j the printed form omits)
+    wall_data: str = "jets"
 
     def __post_init__(self):
         self.dims = tuple(int(n) for n in self.dims)
@@ -377,6 +382,7 @@ class Run:
         else:
             self.f = self._initial(phi0, grad0)
         self._masks = self._unknown_masks()
+        self._axes = self._wall_axes()
 
     @property
     def t(self) -> float:
@@ -425,6 +431,26 @@ class Run:
             masks.append(m)
         return masks
 
+    def _wall_axes(self):
+        """Per population, the lowest axis through which it enters from
+        outside at each node (-1 where it is known): the wall whose data
+        serve the Remark-1 construction."""
+        p = self.p
+        axes = []
+        for k in range(p.q):
+            ax = np.full(p.dims, -1, dtype=np.int64)
+            for j in reversed(range(p.d)):
+                lo, hi = p.bc[j]
+                idx = [slice(None)] * p.d
+                if p.c[k, j] == 1 and lo in (FULLWAY, HALFWAY):
+                    idx[j] = 0
+                    ax[tuple(idx)] = j
+                if p.c[k, j] == -1 and hi in (FULLWAY, HALFWAY):
+                    idx[j] = p.dims[j] - 1
+                    ax[tuple(idx)] = j
+            axes.append(ax)
+        return axes
+
     # -- moments ------------------------------------------------------------
     def phi(self) -> np.ndarray:
         return self.f.sum(axis=0)
@@ -469,12 +495,13 @@ class Run:
             if not m.any():
                 continue
             Xm = self.X[m]
+            ax = self._axes[k][m]
             scheme = self._scheme_of(k)
             if scheme == FULLWAY:
-                fnew[k][m] = self.full_way(k, Xm, t + p.dt)
+                fnew[k][m] = self.full_way(k, Xm, t + p.dt, ax)
             else:
                 xb = Xm - p.c[k] * (p.dx / 2.0)
-                fnew[k][m] = -fstar[p.kbar[k]][m] + self.half_way(k, xb, t)
+                fnew[k][m] = -fstar[p.kbar[k]][m] + self.half_way(k, xb, t, ax)
         self.f = fnew
         self.n += 1
 
@@ -492,7 +519,47 @@ class Run:
         return kinds.pop()
 
     # -- boundary schemes ---------------------------------------------------
-    def full_way(self, k: int, xb: np.ndarray, t: float) -> np.ndarray:
+    def wall_jet(self, xb: np.ndarray, t: float, a: int, b: int, ck: np.ndarray,
+                 axes: Optional[np.ndarray]) -> np.ndarray:
+        """d_t^a (c_k . grad)^b phi* at wall points xb.
+
+        wall_data = "jets": straight from the exact solution.  "tangential"
+        (Remark 1): at a point on a wall of axis j only h = phi* restricted to
+        the wall is used.  The equation d_t phi + u . grad phi = R gives
+        d_j phi = (R - d_t phi - sum_{l != j} u_l d_l phi) / u_j, and on any
+        derivative of phi the same relation without R.  Hence
+        c_k . grad = A + (c_j / u_j) R [on phi itself] with
+        A = alpha . grad_tan + beta d_t, alpha = c_k - (c_j / u_j) u (alpha_j = 0),
+        beta = -c_j / u_j, and
+        d_t^a (c_k . grad)^b phi = sum_i C(b, i) beta^i d_t^(a+i) (alpha . grad)^(b-i) phi
+                                   - [a = 0, b = 1] beta R
+        (the last term removes the R that d_t phi carries).  Every term on the
+        right is a time or tangential derivative of the wall data.
+        """
+        p = self.p
+        if p.wall_data == "jets" or b == 0:
+            return p.field.jet(xb, t, a, b, ck)
+        if p.wall_data != "tangential":
+            raise ValueError(p.wall_data)
+        out = np.zeros(xb.shape[:-1])
+        for j in np.unique(axes):
+            sel = axes == j
+            if p.u[j] == 0.0:
+                raise ValueError("Remark-1 wall data need u_j != 0")
+            beta = -ck[j] / p.u[j]
+            alpha = ck + beta * p.u
+            alpha[j] = 0.0
+            acc = np.zeros(int(sel.sum()))
+            for i in range(b + 1):
+                acc = acc + math.comb(b, i) * beta ** i * p.field.jet(xb[sel], t, a + i, b - i,
+                                                                       alpha)
+            if a == 0 and b == 1:
+                acc = acc - beta * p.R
+            out[sel] = acc
+        return out
+
+    def full_way(self, k: int, xb: np.ndarray, t: float,
+                 axes: Optional[np.ndarray] = None) -> np.ndarray:
         """Eq. (bun1): unknown f_k(x_b, t) at a wall node, order P in {1, 3, 4}."""
         p = self.p
         ck = p.c[k].astype(np.float64)
@@ -501,7 +568,7 @@ class Run:
         Rk = wk * p.R
 
         def J(a, b):  # d_t^a (c_k . grad)^b f_k^eq at (x_b, t)
-            return wk * p.field.jet(xb, t, a, b, ck)
+            return wk * self.wall_jet(xb, t, a, b, ck, axes)
 
         if p.P == 1:
             return J(0, 0)
@@ -514,7 +581,8 @@ class Run:
                + dt ** 3 / 24 * J(3, 0) + dt ** 3 / 24 * J(0, 3))
         return val + dt / 2 * Rk
 
-    def half_way(self, k: int, xb: np.ndarray, t: float) -> np.ndarray:
+    def half_way(self, k: int, xb: np.ndarray, t: float,
+                 axes: Optional[np.ndarray] = None) -> np.ndarray:
         """Right-hand side of eq. (bun2) at (x_b, t), order P in {1, 2, 3, 4}.
 
         All directional derivatives are along c_k; f^eq_k + f^eq_kbar and
@@ -530,10 +598,10 @@ class Run:
         RR = wp * p.R  # R_k + R_kbar
 
         def S(a, b):
-            return wp * p.field.jet(xb, t, a, b, ck)
+            return wp * self.wall_jet(xb, t, a, b, ck, axes)
 
         def Dm(a, b):
-            return wm * p.field.jet(xb, t, a, b, ck)
+            return wm * self.wall_jet(xb, t, a, b, ck, axes)
 
         val = S(0, 0)
         if p.P == 1:

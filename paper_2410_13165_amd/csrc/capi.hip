@@ -293,6 +293,13 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
     return fail(nullptr, LBM_EINVAL, "Dirichlet walls need an analytic field for their data");
   if (scheme != kNoWall && p->field->kind == LBM_FIELD_TANH_BUBBLE)
     return fail(nullptr, LBM_EUNSUPPORTED, "the tanh field supplies no wall derivatives");
+  if (p->wall_data != LBM_WALL_JETS && p->wall_data != LBM_WALL_TANGENTIAL)
+    return fail(nullptr, LBM_EINVAL, "unknown wall_data");
+  if (p->wall_data == LBM_WALL_TANGENTIAL)
+    for (int a = 0; a < d; ++a)
+      if (p->bc[a] != LBM_BC_PERIODIC && !(std::fabs(p->u[a]) > 0.0))
+        return fail(nullptr, LBM_EINVAL,
+                    "tangential wall data need u_j != 0 on every Dirichlet axis j");
 
   lbm_handle* h = new (std::nothrow) lbm_handle();
   if (!h) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
@@ -322,8 +329,10 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
     kp.bc[a] = a < d ? p->bc[a] : 0;
     kp.origin[a] = a < d ? p->origin[a] : 0.0;
     kp.u[a] = a < d ? p->u[a] : 0.0;
+    kp.inv_u[a] = (a < d && p->bc[a] != LBM_BC_PERIODIC && p->u[a] != 0.0) ? 1.0 / p->u[a] : 0.0;
     kp.shift[a] = (a < d && p->bc[a] == LBM_BC_HALFWAY) ? 0.5 : 0.0;
   }
+  kp.wall_data = p->wall_data;
   kp.nodes = static_cast<int>(nodes);
   kp.rows = static_cast<int>(nodes / dims[0]);
   // population planes: the nodes, then (with walls on x_1) one slot per row

@@ -55,6 +55,8 @@ struct KParams {
   double origin[kMaxDim];
   double shift[kMaxDim];   // 1/2 on half-way axes, else 0
   double u[kMaxDim];
+  double inv_u[kMaxDim];   // 1 / u_j on Dirichlet axes (tangential wall data)
+  int wall_data;           // 0: jets of the exact solution; 1: Remark-1 construction
   double phi_ref;          // FP32 mode: mean of phi0
   // rows on a wall of an axis >= 2, listed face by face (see k_wall)
   int nwfaces;

@@ -120,6 +120,19 @@ __device__ __forceinline__ bool outside(const RowInfo<D>& r) {
   return o;
 }
 
+// Lowest axis through whose wall population k enters the node from outside
+// (0 when it enters through none).
+template <int D, int k>
+__device__ __forceinline__ int wall_axis(const RowInfo<D>& r) {
+  constexpr Vec4i c = vel_vec(D, k);
+  int ax = -1;
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a) {
+    if ((c.v[a] == 1 && r.lo[a]) || (c.v[a] == -1 && r.hi[a])) ax = a;
+  }
+  return ax < 0 ? 0 : ax;
+}
+
 template <int D>
 __device__ __forceinline__ bool on_wall(const RowInfo<D>& r) {
   return r.rowwall || r.lo[0] || r.hi[0];
@@ -231,9 +244,17 @@ __device__ void field_initial(const FieldDev& F, const KParams& p, const double 
 // caller adds -f*_kbar(x, t_n).  One sincos (or exp) per mode serves every
 // population: the half-way shift -(dx/2) kappa . c_k is applied by rotating
 // with the per-axis factors of FieldDev::rot.
-template <int D, class Sel>
+//
+// Every derivative of a mode along c_k multiplies it by kappa . c_k.  With
+// tangential wall data (TAN, p.wall_data == 1) that factor is assembled from what
+// the data on the wall of axis j = axis(k) provide, as Remark 1 does with the
+// equation: c_k . grad F = alpha . grad_tan F + beta d_t F with
+// alpha = c_k - (c_kj / u_j) u (tangential, alpha_j = 0) and beta = -c_kj / u_j,
+// i.e. the factor alpha . kappa + beta (-kappa . u).
+template <int D, bool TAN, class Sel, class Axis>
 __device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x)[kMaxDim],
-                                              double t_n, Sel sel, double (&val)[q_of(D)]) {
+                                              double t_n, Sel sel, Axis axis,
+                                              double (&val)[q_of(D)]) {
   constexpr int Q = q_of(D);
   const FieldDev& F = p.field;
   const double dt = p.dt;
@@ -263,8 +284,20 @@ __device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x
       constexpr Vec4i c = vel_vec(D, k);
       if (!sel(k)) return;
       double pc = 0.0;
+      if constexpr (!TAN) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) pc += c.v[a] * F.kvec[j][a];
+        for (int a = 0; a < D; ++a) pc += c.v[a] * F.kvec[j][a];
+      } else {
+        const int ja = axis(k);
+        double r = 0.0;  // c_kj / u_j
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          if (a == ja) r = c.v[a] * p.inv_u[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          if (a != ja) pc += (c.v[a] - r * p.u[a]) * F.kvec[j][a];
+        pc -= r * w;
+      }
       if (full) {
         const double pv = pc + w;  // kappa . (c_k - u)
         const double pv3 = pv * pv * pv;
@@ -332,7 +365,7 @@ constexpr int xface_slot(int D, int k) {
 // rows that lie on a wall of an axis >= 2 and by the x_1 faces through
 // k_xface).  fstar_local(kb) returns the absolute post-collision f*_kb at the
 // node.
-template <int D, class A, class FStarLocal>
+template <int D, bool TAN, class A, class FStarLocal>
 __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, const RowInfo<D>& r,
                                             double t_n, double ref, FStarLocal fstar_local) {
   double x[kMaxDim] = {0.0, 0.0, 0.0, 0.0};
@@ -343,8 +376,14 @@ __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, c
     constexpr int k = decltype(K)::value;
     out[k] = outside<D, k>(r);
   });
+  int ax[q_of(D)];
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    ax[k] = TAN ? wall_axis<D, k>(r) : 0;
+  });
   double val[q_of(D)];
-  wall_analytic<D>(p, x, t_n, [&](int k) { return out[k]; }, val);
+  wall_analytic<D, TAN>(p, x, t_n, [&](int k) { return out[k]; }, [&](int k) { return ax[k]; },
+                        val);
   const bool half = p.scheme == kHalfWay;
   static_for<0, q_of(D)>([&](auto K) {
     constexpr int k = decltype(K)::value;
@@ -366,7 +405,7 @@ __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, c
 //             stored post-collision kbar value of the node),
 // with ref = phi_ref + R t_{n+1} in float32 mode and 0 otherwise.  The split
 // mode keeps float64 values in p.xdata[(side * (2D-1) + slot) * rows + row].
-template <int D, class T>
+template <int D, class T, bool TAN>
 __global__ void __launch_bounds__(256)
     k_xface(T* __restrict__ buf, const KParams p, const double t_n, const int mode) {
   constexpr int S = 2 * D - 1;
@@ -388,7 +427,8 @@ __global__ void __launch_bounds__(256)
   const long long ps = p.pstride;
   const int want = side ? -1 : 1;
   double val[q_of(D)];
-  wall_analytic<D>(p, x, t_n, [&](int k) { return p.cv[k][0] == want; }, val);
+  wall_analytic<D, TAN>(p, x, t_n, [&](int k) { return p.cv[k][0] == want; },
+                        [](int) { return 0; }, val);
   static_for<0, q_of(D)>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int cx = vel_comp(D, k, 0);
@@ -614,7 +654,7 @@ __device__ __forceinline__ int wall_row(const KParams& p, int idx) {
   return row;
 }
 
-template <int D, class T>
+template <int D, class T, bool TAN>
 __global__ void __launch_bounds__(256)
     k_wall(const T* __restrict__ src, T* __restrict__ dst, const KParams p, const double t_n) {
   constexpr int Q = q_of(D);
@@ -635,14 +675,14 @@ __global__ void __launch_bounds__(256)
       constexpr int k = decltype(K)::value;
       f[k] = src[k * ps + node + pull_offset<D, k>(r)];
     });
-    wall_values<D, T>(f, p, r, t_n, ref, [&](int kb) {
+    wall_values<D, TAN, T>(f, p, r, t_n, ref, [&](int kb) {
       return static_cast<double>(src[kb * ps + node]) + p.omega[kb] * ref;
     });
     collide_store<D, T>(f, dst, ps, node, p);
   }
 }
 
-template <int D>
+template <int D, bool TAN>
 __global__ void __launch_bounds__(256)
     k_wall_split(const float* __restrict__ gsrc, float* __restrict__ gdst,
                  const double* __restrict__ phisrc, double* __restrict__ phidst, const KParams p,
@@ -659,7 +699,7 @@ __global__ void __launch_bounds__(256)
     const int node = r.rowbase + x;
     double f[Q];
     split_pull<D>(f, gsrc, phisrc, ps, node, r, p);
-    wall_values<D, double>(f, p, r, t_n, 0.0, [&](int kb) {
+    wall_values<D, TAN, double>(f, p, r, t_n, 0.0, [&](int kb) {
       return split_fstar<D>(gsrc, phisrc, ps, node, kb, p);
     });
     split_store<D>(f, gdst, phidst, ps, node, p);
@@ -899,10 +939,10 @@ static unsigned grid_for(long long nodes, int threads) {
   return static_cast<unsigned>(b);
 }
 
-template <int D>
-static hipError_t step_d(const KParams& p, int mode, const void* src, void* dst,
-                         const double* phi_src, double* phi_dst, long long n,
-                         hipStream_t stream, hipEvent_t* ev) {
+template <int D, bool TAN>
+static hipError_t step_dt(const KParams& p, int mode, const void* src, void* dst,
+                          const double* phi_src, double* phi_dst, long long n,
+                          hipStream_t stream, hipEvent_t* ev) {
   const LaunchShape s = step_shape(p);
   const dim3 block(s.tx, s.ty), grid(s.blocks);
   const dim3 wgrid(static_cast<unsigned>((p.wall_rows + s.ty - 1) / s.ty));
@@ -913,10 +953,10 @@ static hipError_t step_d(const KParams& p, int mode, const void* src, void* dst,
   if (p.bc[0] != 0) {
     const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
     if (mode == kFP64)
-      hipLaunchKernelGGL((k_xface<D, double>), dim3(xb), dim3(256), 0, stream,
+      hipLaunchKernelGGL((k_xface<D, double, TAN>), dim3(xb), dim3(256), 0, stream,
                          static_cast<double*>(const_cast<void*>(src)), p, t_n, mode);
     else
-      hipLaunchKernelGGL((k_xface<D, float>), dim3(xb), dim3(256), 0, stream,
+      hipLaunchKernelGGL((k_xface<D, float, TAN>), dim3(xb), dim3(256), 0, stream,
                          static_cast<float*>(const_cast<void*>(src)), p, t_n, mode);
   }
   mark(0);
@@ -926,25 +966,34 @@ static hipError_t step_d(const KParams& p, int mode, const void* src, void* dst,
     hipLaunchKernelGGL((k_step<D, double>), grid, block, 0, stream, a, b, p);
     mark(1);
     if (p.wall_rows > 0)
-      hipLaunchKernelGGL((k_wall<D, double>), wgrid, block, 0, stream, a, b, p, t_n);
+      hipLaunchKernelGGL((k_wall<D, double, TAN>), wgrid, block, 0, stream, a, b, p, t_n);
   } else if (mode == kFP32) {
     auto* a = static_cast<const float*>(src);
     auto* b = static_cast<float*>(dst);
     hipLaunchKernelGGL((k_step<D, float>), grid, block, 0, stream, a, b, p);
     mark(1);
     if (p.wall_rows > 0)
-      hipLaunchKernelGGL((k_wall<D, float>), wgrid, block, 0, stream, a, b, p, t_n);
+      hipLaunchKernelGGL((k_wall<D, float, TAN>), wgrid, block, 0, stream, a, b, p, t_n);
   } else {
     auto* a = static_cast<const float*>(src);
     auto* b = static_cast<float*>(dst);
     hipLaunchKernelGGL((k_step_split<D>), grid, block, 0, stream, a, b, phi_src, phi_dst, p);
     mark(1);
     if (p.wall_rows > 0)
-      hipLaunchKernelGGL((k_wall_split<D>), wgrid, block, 0, stream, a, b, phi_src, phi_dst, p,
-                         t_n);
+      hipLaunchKernelGGL((k_wall_split<D, TAN>), wgrid, block, 0, stream, a, b, phi_src, phi_dst,
+                         p, t_n);
   }
   mark(2);
   return hipGetLastError();
+}
+
+template <int D>
+static hipError_t step_d(const KParams& p, int mode, const void* src, void* dst,
+                         const double* phi_src, double* phi_dst, long long n,
+                         hipStream_t stream, hipEvent_t* ev) {
+  if (p.wall_data)
+    return step_dt<D, true>(p, mode, src, dst, phi_src, phi_dst, n, stream, ev);
+  return step_dt<D, false>(p, mode, src, dst, phi_src, phi_dst, n, stream, ev);
 }
 
 hipError_t launch_step(const KParams& p, int mode, const void* src, void* dst,

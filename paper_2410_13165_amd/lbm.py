@@ -25,6 +25,7 @@ NSCALARS = 8
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5
 BC = {"periodic": 0, "fullway": 1, "halfway": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_split": 2}
+WALL_DATA = {"jets": 0, "tangential": 1}
 FIELD = {"none": 0, "cos_sum": 1, "exp_sum": 2, "tanh_bubble": 3}
 
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -48,7 +49,7 @@ class LbmParams(C.Structure):
         ("bc", C.c_int32 * MAX_DIM), ("bc_order", C.c_int32), ("init_order", C.c_int32),
         ("precision", C.c_int32), ("field", C.POINTER(LbmField)),
         ("alloc", _ALLOC), ("free_fn", _FREE), ("alloc_ctx", C.c_void_p),
-        ("stream", C.c_void_p),
+        ("stream", C.c_void_p), ("wall_data", C.c_int32),
     ]
 
 
@@ -207,7 +208,7 @@ class Lattice:
                  u: Sequence[float], R: float = 0.0, origin: Optional[Sequence[float]] = None,
                  bc: Optional[Sequence[str]] = None, P: int = 4, K: int = 3,
                  precision: str = "fp64", field=None, g: float = 0.5,
-                 m4: Optional[float] = None, device=None):
+                 m4: Optional[float] = None, wall_data: str = "jets", device=None):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -236,6 +237,7 @@ class Lattice:
         p.init_order = int(K)
         p.precision = PRECISION[precision]
         self.precision = precision
+        p.wall_data = WALL_DATA[wall_data]
 
         self._field_keep = []
         if field is not None:

@@ -25,22 +25,22 @@ def oracle_field(spec: dict, d: int):
 
 
 def oracle_problem(d, dims, dx, spec=None, u=None, R=None, tau=0.5, bc=None, P=4, K=3,
-                   origin=None, faces=None, shift=None):
+                   origin=None, faces=None, shift=None, wall_data="jets"):
     u = spec["u"] if u is None else u
     R = spec.get("R", 0.0) if (R is None and spec is not None) else (R or 0.0)
     if faces is None:
         faces = [(b, b) for b in (bc or ["periodic"] * d)]
     return O.Problem(d, dims, dx, u, R=R, tau=tau, origin=origin, bc=faces, P=P, K=K,
-                     field=oracle_field(spec, d), shift=shift)
+                     field=oracle_field(spec, d), shift=shift, wall_data=wall_data)
 
 
 def gpu_lattice(d, dims, dx, spec=None, u=None, R=None, tau=0.5, bc=None, P=4, K=3,
-                origin=None, precision="fp64"):
+                origin=None, precision="fp64", wall_data="jets"):
     from paper_2410_13165_amd import Lattice
     u = spec["u"] if u is None else u
     R = spec.get("R", 0.0) if (R is None and spec is not None) else (R or 0.0)
     return Lattice(d, dims, tau, dx=dx, u=u, R=R, origin=origin, bc=bc, P=P, K=K,
-                   precision=precision, field=spec)
+                   precision=precision, field=spec, wall_data=wall_data)
 
 
 def to_oracle_order(arr: np.ndarray) -> np.ndarray:

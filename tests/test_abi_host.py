@@ -53,7 +53,7 @@ int main(void) {
   P(lbm_params, g); P(lbm_params, m4); P(lbm_params, use_m4); P(lbm_params, bc);
   P(lbm_params, bc_order); P(lbm_params, init_order); P(lbm_params, precision);
   P(lbm_params, field); P(lbm_params, alloc); P(lbm_params, free_fn);
-  P(lbm_params, alloc_ctx); P(lbm_params, stream);
+  P(lbm_params, alloc_ctx); P(lbm_params, stream); P(lbm_params, wall_data);
   P(lbm_field, n_modes); P(lbm_field, amps); P(lbm_field, kvecs); P(lbm_field, phases);
   P(lbm_field, Rr); P(lbm_field, W); P(lbm_field, center);
   P(lbm_info_t, dims); P(lbm_info_t, nodes); P(lbm_info_t, step); P(lbm_info_t, omega);
@@ -130,6 +130,27 @@ def test_create_rejects_walls_without_field_and_mixed_schemes():
     assert rc == B.EINVAL and "init_order" in err
     rc, h, err = _create(2, (8, 8), 0.5, dx=0.0)
     assert rc == B.EINVAL and "dx" in err
+
+
+def test_tangential_wall_data_needs_nonzero_normal_velocity():
+    lib = B.load_library()
+    p = B.LbmParams()
+    lib.lbm_params_default(C.byref(p))
+    amps = (C.c_double * 1)(1.0)
+    kv = (C.c_double * 2)(1.0, 2.0)
+    f = B.LbmField()
+    f.kind, f.n_modes, f.amps, f.kvecs = 1, 1, amps, kv
+    p.field = C.pointer(f)
+    p.bc[0], p.bc[1] = 0, 1
+    p.u[0], p.u[1] = 0.1, 0.0
+    p.wall_data = 1
+    arr = (C.c_int64 * 4)(8, 8, 1, 1)
+    h = C.c_void_p()
+    assert lib.lbm_create(2, arr, 0.5, C.byref(p), C.byref(h)) == B.EINVAL
+    assert "u_j != 0" in lib.lbm_last_error(None).decode() and not h.value
+    p.wall_data = 7
+    assert lib.lbm_create(2, arr, 0.5, C.byref(p), C.byref(h)) == B.EINVAL
+    assert "wall_data" in lib.lbm_last_error(None).decode()
 
 
 def test_null_handle_calls_fail_cleanly():

@@ -27,14 +27,15 @@ def _phi(lat):
 
 
 def _check_pair(d, dims, dx, spec, steps, bc=None, P=4, K=3, tau=0.5, precision="fp64",
-                origin=None, populations=True):
-    prob = oracle_problem(d, dims, dx, spec, tau=tau, bc=bc, P=P, K=K, origin=origin)
+                origin=None, populations=True, wall_data="jets"):
+    prob = oracle_problem(d, dims, dx, spec, tau=tau, bc=bc, P=P, K=K, origin=origin,
+                          wall_data=wall_data)
     run = O.Run(prob)
     lat = gpu_lattice(d, dims, dx, spec, tau=tau, bc=bc, P=P, K=K, origin=origin,
-                      precision=precision)
+                      precision=precision, wall_data=wall_data)
     try:
         print(f"[parity] d={d} dims={dims} bc={bc} P={P} K={K} tau={tau} {precision} "
-              f"steps={steps}", flush=True)
+              f"steps={steps} wall_data={wall_data}", flush=True)
         # step 0, then a few steps, then the rest
         for n in (0, 1, steps):
             lat.step(n - lat.info()["step"])
@@ -99,6 +100,39 @@ def test_mixed_periodic_and_dirichlet_axes(scheme):
 def test_dirichlet_reduced_precision(scheme, precision):
     spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0, seed=41, kmax=1.0)
     _check_pair(3, (45, 22, 19), 1.0 / 44, spec, 80, bc=[scheme] * 3, precision=precision)
+
+
+@pytest.mark.parametrize("scheme", ["fullway", "halfway"])
+@pytest.mark.parametrize("d,dims", [(2, (41, 30)), (3, (23, 17, 19)), (4, (9, 8, 7, 6))])
+def test_tangential_wall_data(scheme, d, dims):
+    """Remark 1: walls fed only by the data on the wall (time and tangential
+    derivatives; normal ones from the equation).  GPU against the oracle's
+    Remark-1 construction, and against the GPU's own jets path to rounding."""
+    u = [0.05, -0.1, 0.08, 0.03][:d]
+    spec = inputs.random_cosines(d, u, 0.6, seed=50 + d, kmax=1.0)
+    dx = 1.0 / (dims[0] - 1)
+    _check_pair(d, dims, dx, spec, 12, bc=[scheme] * d, wall_data="tangential")
+    a = gpu_lattice(d, dims, dx, spec, bc=[scheme] * d, wall_data="tangential")
+    b = gpu_lattice(d, dims, dx, spec, bc=[scheme] * d)
+    try:
+        a.step(30)
+        b.step(30)
+        assert rel_l2(_phi(a), _phi(b)) <= 1e-13
+    finally:
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_split"])
+def test_tangential_wall_data_reduced_precision_and_lower_order(precision):
+    spec = inputs.example1([0.1, 0.1])
+    _check_pair(2, (21, 21), 1.0 / 20, spec, 40, bc=["fullway"] * 2, P=3,
+                wall_data="tangential")
+    _check_pair(2, (20, 20), 1.0 / 20, spec, 40, bc=["halfway"] * 2, P=3,
+                wall_data="tangential")
+    _check_pair(3, (33, 19, 17), 1.0 / 32, inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0,
+                                                                 seed=57, kmax=1.0),
+                60, bc=["fullway"] * 3, precision=precision, wall_data="tangential")
 
 
 def test_example1_source_term_fp32_reference():

@@ -393,6 +393,60 @@ def test_jets_against_finite_differences(kind):
             assert abs(got - ref) < 2e-4 * max(1.0, abs(ref)), (a, b, got, ref)
 
 
+# ------------------------------------------------- Remark-1 wall data ------
+
+@pytest.mark.parametrize("kind", ["cos_sum", "exp_sum"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_remark1_jets_equal_exact_jets(kind, d):
+    """Remark 1 (with the 1/u_j restored): on a wall of axis j the time and
+    tangential derivatives of the data alone reproduce every mixed jet
+    d_t^a (c_k . grad)^b phi* with a + b <= 3, including the R term."""
+    rng = np.random.default_rng(80 + d)
+    u = rng.uniform(0.05, 0.3, d) * rng.choice([-1, 1], d)
+    fld = O.ExactField(kind, u=u, R=0.9, amps=rng.normal(size=3),
+                       kvecs=rng.uniform(-2, 2, (3, d)), phases=rng.uniform(0, 6, 3))
+    prob = O.Problem(d, (4,) * d, 0.1, u, R=0.9, bc=[("fullway", "fullway")] * d,
+                     field=fld, wall_data="tangential")
+    run = O.Run(prob)
+    t = 0.31
+    for j in range(d):
+        xb = rng.uniform(-1, 1, (5, d))
+        xb[:, j] = 0.0
+        axes = np.full(5, j)
+        for k in range(prob.q):
+            ck = prob.c[k].astype(float)
+            for a in range(4):
+                for b in range(4 - a):
+                    got = run.wall_jet(xb, t, a, b, ck, axes)
+                    ref = fld.jet(xb, t, a, b, ck)
+                    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), \
+                        (j, k, a, b)
+
+
+@pytest.mark.parametrize("scheme", ["fullway", "halfway"])
+def test_remark1_run_equals_jets_run(scheme):
+    """Whole runs with the two kinds of wall data agree to rounding."""
+    u = np.array([0.12, -0.07, 0.05])
+    rng = np.random.default_rng(5)
+    fld = O.ExactField("cos_sum", u=u, R=0.4, amps=rng.normal(size=2),
+                       kvecs=rng.uniform(-3, 3, (2, 3)), phases=rng.uniform(0, 6, 2))
+    out = []
+    for wd in ("jets", "tangential"):
+        prob = O.Problem(3, (6, 5, 5), 0.1, u, R=0.4, bc=[(scheme, scheme)] * 3, field=fld,
+                         wall_data=wd)
+        out.append(O.Run(prob).step(4).phi())
+    assert np.max(np.abs(out[0] - out[1])) <= 1e-13 * np.max(np.abs(out[0]))
+
+
+def test_remark1_needs_nonzero_normal_velocity():
+    fld = O.ExactField("cos_sum", u=[0.1, 0.0], amps=[1.0], kvecs=[[1.0, 2.0]])
+    prob = O.Problem(2, (5, 5), 0.1, [0.1, 0.0], bc=[("periodic", "periodic"),
+                                                     ("fullway", "fullway")],
+                     field=fld, wall_data="tangential")
+    with pytest.raises(ValueError, match="u_j"):
+        O.Run(prob).step(1)
+
+
 # --------------------------------------------------------- wall schemes -----
 
 def _exp_prob(u, scheme, P, R=0.3, dx=0.05):
