@@ -9,12 +9,15 @@ kernel); `value` is the float32-storage throughput in million lattice updates
 per second with all state resident in HBM.  The float64 and float32-split
 storage modes are measured on the same workload for the precision comparison.
 
-The roofline entry is for the dominant kernel (the bulk stream-collide): its
-algorithmic bytes per launch (2 q sizeof(float) per node of the (n-2)^2 rows
-off the y/z walls) divided by its
+The roofline entry is for the dominant kernel (the bulk stream-collide; in
+float32 it advances two time steps per launch, keeping the intermediate state
+in LDS): its algorithmic bytes per launch (2 q sizeof(float) per node of the
+(n-2)^2 rows off the y/z walls, times the steps per launch) divided by its
 average duration from HIP events recorded around every launch on the
-library's stream during the timed region.  The CPU baseline is the float64
-oracle on a bounded sample of the same workload.
+library's stream during the timed region.  Because the two-step kernel moves
+fewer bytes than two single steps, the measured HBM traffic (from the
+committed counter profile) is reported beside it.  The CPU baseline is the
+float64 oracle on a bounded sample of the same workload.
 
 Prints one JSON line.
 """
@@ -89,8 +92,13 @@ def run_mode(precision: str, steps: int, warmup: int, n: int):
     bulk_nodes = (n - 2) ** 2 * n
     q = info["q"]
     esize = 8 if precision == "fp64" else 4
-    bulk_bytes = bulk_nodes * 2 * q * esize + (bulk_nodes * 16 if precision == "fp32_split" else 0)
-    bulk_s = prof["bulk_ms"] / prof["steps"] / 1e3
+    bulk_bytes_step = bulk_nodes * 2 * q * esize + (bulk_nodes * 16 if precision == "fp32_split"
+                                                     else 0)
+    # a bulk launch covers steps_per_launch time steps (two when the lattice
+    # advances in fused pairs); its algorithmic bytes are those of its steps
+    steps_per_launch = prof["steps"] / prof["launches"]
+    bulk_bytes = bulk_bytes_step * steps_per_launch
+    bulk_s = prof["bulk_ms"] / prof["launches"] / 1e3
     wall_s = prof["wall_ms"] / prof["steps"] / 1e3
     return {
         "precision": precision,
@@ -99,6 +107,7 @@ def run_mode(precision: str, steps: int, warmup: int, n: int):
         "seconds": seconds,
         "bytes_per_lu": info["bytes_per_lu"],
         "hbm_frac_step": nodes * steps * info["bytes_per_lu"] / seconds / (HBM_PEAK_GBS * 1e9),
+        "steps_per_launch": steps_per_launch,
         "bulk_ms": bulk_s * 1e3,
         "wall_ms": wall_s * 1e3,
         "bulk_bytes_per_launch": bulk_bytes,
@@ -336,6 +345,10 @@ def main(argv=None):
               f"ratio {adj['ratio']:.3f}", file=sys.stderr, flush=True)
 
     traffic = committed_traffic(head["bulk_bytes_per_launch"]) if modes[0] == "fp32" else None
+    if head["steps_per_launch"] == 2:
+        kernel = "k_fused2<false> (two stream-collide steps per pass, float32)"
+    else:
+        kernel = f"k_step<3,{'float' if modes[0] != 'fp64' else 'double'}> (bulk stream-collide)"
     roofline = {
         "bound": "hbm",
         "achieved": round(head["bulk_gbs"], 1),
@@ -343,10 +356,14 @@ def main(argv=None):
         "unit": "GB/s",
         "frac": round(head["bulk_gbs"] / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": f"k_step<3,{'float' if modes[0] != 'fp64' else 'double'}> (bulk stream-collide)",
+        "kernel": kernel,
+        "steps_per_launch": head["steps_per_launch"],
         "bytes_per_launch": head["bulk_bytes_per_launch"],
         "avg_launch_ms": round(head["bulk_ms"], 4),
     }
+    if traffic:
+        # measured HBM bytes per launch over the same duration
+        roofline["hbm_gbs_measured"] = round(traffic / (head["bulk_ms"] / 1e3) / 1e9, 1)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_nodes, args.cpu_steps)

@@ -134,6 +134,10 @@ typedef struct {
   void* alloc_ctx;
   void* stream;                 /* hipStream_t used for all work, borrowed            */
   int32_t wall_data;            /* lbm_wall_data; default LBM_WALL_JETS               */
+  int32_t steps_per_pass;       /* 2 (default): float32 lattices with d = 3 advance two
+                                   time steps per pass of the bulk kernel (bitwise the
+                                   same result, about half the HBM traffic); 1: one
+                                   step per pass.  Other lattices always use 1.       */
 } lbm_params;
 
 typedef struct {
@@ -148,14 +152,14 @@ typedef struct {
   double s, dt;
   double phi_ref;               /* LBM_FP32: phi_mean of the deviation reference      */
   int32_t bytes_per_lu;         /* algorithmic HBM bytes per lattice update of a step */
-  int32_t reserved;
+  int32_t steps_per_pass;       /* time steps per bulk-kernel pass lbm_step uses      */
   int64_t pstride;              /* elements between population planes in the state
                                    blob of lbm_get_state (nodes first, then padding) */
 } lbm_info_t;
 
 /* Fill p with defaults: dx = 1, origin 0, u 0, R 0, g = 1/2, all axes periodic,
    P = 4, K = 3, LBM_FP64, no field, hipMalloc/hipFree, null stream,
-   LBM_WALL_JETS. */
+   LBM_WALL_JETS, steps_per_pass = 2. */
 void lbm_params_default(lbm_params* p);
 
 /* Create a lattice with d in 1..4 axes of dims[0..d-1] nodes and relaxation time
@@ -178,8 +182,13 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p,
    the step counter to 0. */
 int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_phi0_dev);
 
-/* Advance n >= 0 time steps: n launches of the fused pull-stream + collide
-   kernel with the wall schemes applied inline.  Asynchronous on the stream. */
+/* Advance n >= 0 time steps of the fused pull-stream + collide kernel with
+   the wall schemes applied inline.  With steps_per_pass = 2 (float32, d = 3)
+   the steps go in pairs through one bulk pass that keeps the intermediate
+   state in LDS, plus one single step when n is odd; while a tape is recording
+   (lbm_tape_begin) every step is single.  The first paired call allocates a
+   scratch state buffer (the size of one state) through the allocator
+   (LBM_ENOMEM if that fails).  Asynchronous on the stream. */
 int lbm_step(lbm_handle* h, int64_t n);
 
 /* Moments of the current state t_n.
@@ -206,16 +215,18 @@ int lbm_get_state(const lbm_handle* h, void* dst_dev);
 int lbm_set_state(lbm_handle* h, const void* src_dev, int64_t step);
 
 /* Kernel timing with HIP events recorded on the lattice's stream, for
-   benchmarks.  After lbm_profile_begin, each of the next max_steps steps
-   records events before the bulk kernel, between the bulk and the wall
-   kernel, and after the wall kernel.  lbm_profile_end synchronises the stream,
-   returns the summed durations in milliseconds of the bulk launches
-   (bulk_ms) and of the wall launches (wall_ms, 0 without Dirichlet axes) and
-   the number of profiled steps, and releases the events.  Both outputs are
-   nullable.  Errors: LBM_EINVAL (max_steps < 1 or > 2^20, profiling already
-   active / not active), LBM_EDEVICE. */
-int lbm_profile_begin(lbm_handle* h, int64_t max_steps);
-int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* steps);
+   benchmarks.  After lbm_profile_begin, each of the next max_launches bulk
+   passes (one step, or two with steps_per_pass = 2) records events before the
+   bulk kernel, after it, and after the wall kernel of its last step.
+   lbm_profile_end synchronises the stream and returns the summed durations in
+   milliseconds of the bulk passes (bulk_ms) and of the wall kernels after them
+   (wall_ms, 0 without Dirichlet axes >= 2), the number of time steps those
+   passes covered (steps) and the number of passes (launches), and releases the
+   events.  All outputs are nullable.  Errors: LBM_EINVAL (max_launches < 1 or
+   > 2^20, profiling already active / not active), LBM_EDEVICE. */
+int lbm_profile_begin(lbm_handle* h, int64_t max_launches);
+int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* steps,
+                    int64_t* launches);
 
 /* Gradients of a final-time misfit L(phi^N) by the adjoint (transposed)
    stream-collide (see adjoint.hip): the step is linear in the populations,

@@ -47,8 +47,11 @@ struct lbm_handle {
   std::vector<void*> tape_ckpt;
   // kernel timing (lbm_profile_begin / lbm_profile_end): 3 events per step
   std::vector<hipEvent_t> prof_ev;
-  int64_t prof_cap = 0, prof_used = 0;
+  int64_t prof_cap = 0, prof_used = 0, prof_steps = 0;
   bool profiling = false;
+  // two steps per bulk pass (float32, d = 3): scratch state for the wall rows
+  int steps_per_pass = 1;
+  void* fuse_buf = nullptr;
 };
 
 static thread_local std::string g_create_error;
@@ -101,8 +104,10 @@ void release(lbm_handle* h) {
   dev_free(h, h->partial);
   dev_free(h, h->result);
   dev_free(h, h->kp.xdata);
+  dev_free(h, h->fuse_buf);
   h->partial = h->result = nullptr;
   h->kp.xdata = nullptr;
+  h->fuse_buf = nullptr;
 }
 
 // Copy the analytic field into the kernel parameter block.
@@ -252,6 +257,7 @@ void lbm_params_default(lbm_params* p) {
   p->bc_order = 4;
   p->init_order = 3;
   p->precision = LBM_FP64;
+  p->steps_per_pass = 2;
 }
 
 int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_handle** out) {
@@ -295,6 +301,8 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
     return fail(nullptr, LBM_EUNSUPPORTED, "the tanh field supplies no wall derivatives");
   if (p->wall_data != LBM_WALL_JETS && p->wall_data != LBM_WALL_TANGENTIAL)
     return fail(nullptr, LBM_EINVAL, "unknown wall_data");
+  if (p->steps_per_pass != 1 && p->steps_per_pass != 2)
+    return fail(nullptr, LBM_EINVAL, "steps_per_pass must be 1 or 2");
   if (p->wall_data == LBM_WALL_TANGENTIAL)
     for (int a = 0; a < d; ++a)
       if (p->bc[a] != LBM_BC_PERIODIC && !(std::fabs(p->u[a]) > 0.0))
@@ -307,6 +315,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   h->q = q_of(d);
   h->nodes = nodes;
   h->precision = p->precision;
+  h->steps_per_pass = (p->steps_per_pass == 2 && p->precision == LBM_FP32 && d == 3) ? 2 : 1;
   h->stream = static_cast<hipStream_t>(p->stream);
   h->alloc = p->alloc;
   h->free_fn = p->free_fn;
@@ -463,18 +472,32 @@ int lbm_step(lbm_handle* h, int64_t n) {
   if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
   if (h->batch_member) return fail(h, LBM_EINVAL, "batch instances are stepped by lbm_batch_step");
   if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state (call lbm_set_initial)");
-  for (int64_t i = 0; i < n; ++i) {
+  // pairs of steps in one bulk pass where the lattice allows it (not while a
+  // tape records checkpoints, which fall on single steps)
+  const bool pairs = h->steps_per_pass == 2 && !h->tape_active;
+  if (pairs && n >= 2 && !h->fuse_buf) {
+    h->fuse_buf = dev_alloc(h, pop_bytes(h));
+    if (!h->fuse_buf) return fail(h, LBM_ENOMEM, "scratch state for two-step passes");
+  }
+  int64_t i = 0;
+  while (i < n) {
     const int src = h->cur, dst = 1 - h->cur;
+    const int64_t todo = (pairs && n - i >= 2) ? 2 : 1;
     hipEvent_t* ev = nullptr;
     if (h->profiling && h->prof_used < h->prof_cap) {
       ev = &h->prof_ev[3 * h->prof_used];
       ++h->prof_used;
+      h->prof_steps += todo;
     }
-    hipError_t e = launch_step(h->kp, h->precision, h->buf[src], h->buf[dst], h->phib[src],
-                               h->phib[dst], h->step, h->stream, ev);
+    hipError_t e = (todo == 2)
+                       ? launch_fused_pair(h->kp, h->buf[src], h->buf[dst], h->fuse_buf, h->step,
+                                           h->stream, ev)
+                       : launch_step(h->kp, h->precision, h->buf[src], h->buf[dst],
+                                     h->phib[src], h->phib[dst], h->step, h->stream, ev);
     if (e != hipSuccess) return hip_fail(h, e, "step kernel");
     h->cur = dst;
-    ++h->step;
+    h->step += todo;
+    i += todo;
     if (h->tape_active && (h->step - h->tape_start) % h->tape_every == 0) {
       int rc = tape_push(h);
       if (rc != LBM_OK) return rc;
@@ -526,6 +549,7 @@ int lbm_info(const lbm_handle* h, lbm_info_t* out) {
   const int es = static_cast<int>(elem_size(h->precision));
   out->bytes_per_lu = 2 * h->q * es + (h->precision == LBM_FP32_SPLIT ? 16 : 0);
   out->pstride = h->kp.pstride;
+  out->steps_per_pass = h->steps_per_pass;
   return LBM_OK;
 }
 
@@ -567,7 +591,7 @@ namespace {
 void destroy_events(lbm_handle* h) {
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
   h->prof_ev.clear();
-  h->prof_cap = h->prof_used = 0;
+  h->prof_cap = h->prof_used = h->prof_steps = 0;
   h->profiling = false;
 }
 }  // namespace
@@ -587,11 +611,13 @@ int lbm_profile_begin(lbm_handle* h, int64_t max_steps) {
   }
   h->prof_cap = max_steps;
   h->prof_used = 0;
+  h->prof_steps = 0;
   h->profiling = true;
   return LBM_OK;
 }
 
-int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* steps) {
+int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* steps,
+                    int64_t* launches) {
   if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
   if (!h->profiling) return fail(h, LBM_EINVAL, "profiling not active");
   hipError_t e = hipStreamSynchronize(h->stream);
@@ -613,7 +639,8 @@ int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* st
   }
   if (bulk_ms) *bulk_ms = b;
   if (wall_ms) *wall_ms = h->kp.wall_rows > 0 ? w : 0.0;
-  if (steps) *steps = h->prof_used;
+  if (steps) *steps = h->prof_steps;
+  if (launches) *launches = h->prof_used;
   destroy_events(h);
   return LBM_OK;
 }

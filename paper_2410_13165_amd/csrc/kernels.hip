@@ -449,14 +449,15 @@ __global__ void __launch_bounds__(256)
 
 // ------------------------------------------------------------ step kernels --
 
-// Collision of the pulled pre-collision populations and store of the
-// post-collision ones (non-temporal stores: nothing rereads them this step).  float64: f*_k = (1-s) f_k + s omega_k phi + dt omega_k R.
+// Collision of the pulled pre-collision populations (collide_vals, in place)
+// and store of the post-collision ones (collide_store; non-temporal stores:
+// nothing rereads them this step).
+// float64: f*_k = (1-s) f_k + s omega_k phi + dt omega_k R.
 // float32 stores deviations from the uniform exact state omega_k (phi_ref + R t),
 // which is a fixed point of stream + collide, so the deviations follow the same
 // update without the source term; phi is summed with TwoSum compensation.
 template <int D, class T>
-__device__ __forceinline__ void collide_store(T (&f)[q_of(D)], T* __restrict__ dst, long long ps,
-                                              int node, const KParams& p) {
+__device__ __forceinline__ void collide_vals(T (&f)[q_of(D)], const KParams& p) {
   constexpr int Q = q_of(D);
   if constexpr (std::is_same<T, float>::value) {
     float sum = f[0], comp = 0.0f;
@@ -469,8 +470,7 @@ __device__ __forceinline__ void collide_store(T (&f)[q_of(D)], T* __restrict__ d
     const float phi = sum + comp;
     const float oms = 1.0f - p.s_f;
 #pragma unroll
-    for (int k = 0; k < Q; ++k)
-      __builtin_nontemporal_store(fmaf(p.s_f * p.omega_f[k], phi, oms * f[k]), dst + k * ps + node);
+    for (int k = 0; k < Q; ++k) f[k] = fmaf(p.s_f * p.omega_f[k], phi, oms * f[k]);
   } else {
     double phi = 0.0;
 #pragma unroll
@@ -478,10 +478,16 @@ __device__ __forceinline__ void collide_store(T (&f)[q_of(D)], T* __restrict__ d
     const double oms = 1.0 - p.s;
     const double dtR = p.dt * p.R;
 #pragma unroll
-    for (int k = 0; k < Q; ++k)
-      __builtin_nontemporal_store(fma(p.s * p.omega[k], phi, fma(oms, f[k], dtR * p.omega[k])),
-                                  dst + k * ps + node);
+    for (int k = 0; k < Q; ++k) f[k] = fma(p.s * p.omega[k], phi, fma(oms, f[k], dtR * p.omega[k]));
   }
+}
+
+template <int D, class T>
+__device__ __forceinline__ void collide_store(T (&f)[q_of(D)], T* __restrict__ dst, long long ps,
+                                              int node, const KParams& p) {
+  collide_vals<D, T>(f, p);
+#pragma unroll
+  for (int k = 0; k < q_of(D); ++k) __builtin_nontemporal_store(f[k], dst + k * ps + node);
 }
 
 // Bulk rows: post-collision populations stored (float64, or float32
@@ -532,6 +538,189 @@ __global__ void __launch_bounds__(256)
   const int row = blockIdx.x * blockDim.y + threadIdx.y;
   if (row >= p.rows) return;
   step_row<D, T>(src, dst, p, row);
+}
+
+// ------------------------------------------------------ two fused steps --
+//
+// Two time steps t_n -> t_{n+2} in one pass (float32 storage, d = 3), so each
+// stored population is read and written about once per two steps instead of
+// once per step.  A block owns an x_1-x_2 tile of kFuseTX x TY output nodes and
+// a chunk of x_3 planes, and marches along x_3: for step-1 plane z it updates
+// the tile plus a one-node halo (from A, the state at t_n) into LDS, then
+// updates output plane z - 1 of step 2 by pulling from the LDS planes z - 2,
+// z - 1 and z, and stores it to B.  Each plane's step-1 values stay in LDS only
+// as long as step 2 needs them: populations with c_3 = 0 for two planes, c_3 =
+// +1 for three, c_3 = -1 for one (two with half-way walls, whose x_1 faces need
+// the node's own step-1 value of the opposite population).
+//
+// Rows on a Dirichlet wall of x_2 or x_3 are not updated here.  Their step-1
+// values come from k_wall(A -> C) launched before, and k_wall(C -> B) updates
+// them for step 2 afterwards; for that second launch this kernel also stores
+// its step-1 values of the rows next to those walls in C.  The x_1-face wall
+// data of step 1 are in A's row slots and those of step 2 in B's (k_xface on
+// both before the launch).  Every node goes through exactly the arithmetic of
+// k_step, so the result is bitwise that of two single steps.
+constexpr int kFuseTX = 64;
+constexpr int kFuseZChunk = 64;
+template <bool HALF>
+struct FuseShape;
+template <>
+struct FuseShape<false> {
+  static constexpr int TY = 13, NT = 1024, SLOTS = 38;
+};
+template <>
+struct FuseShape<true> {
+  static constexpr int TY = 11, NT = 896, SLOTS = 43;
+};
+
+// index of population k among those with the same c_3
+constexpr int cz_index(int k) {
+  const int cz = vel_comp(3, k, 2);
+  int idx = 0;
+  for (int m = 0; m < k; ++m)
+    if (vel_comp(3, m, 2) == cz) ++idx;
+  return idx;
+}
+
+// LDS plane slot of population k for the step-1 plane produced at iteration it
+template <bool HALF, int k>
+__device__ __forceinline__ int fuse_slot(int it) {
+  constexpr int cz = vel_comp(3, k, 2);
+  constexpr int i = cz_index(k);
+  if constexpr (cz == 0) return 2 * i + (it & 1);
+  else if constexpr (cz == 1) return 18 + 3 * i + it % 3;
+  else if constexpr (HALF) return 33 + 2 * i + (it & 1);
+  else return 33 + i;
+}
+
+__device__ __forceinline__ int fuse_wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+template <bool HALF>
+__global__ void __launch_bounds__(FuseShape<HALF>::NT)
+    k_fused2(const float* __restrict__ A, float* __restrict__ B, float* __restrict__ C,
+             const KParams p) {
+  using S = FuseShape<HALF>;
+  constexpr int D = 3, Q = q_of(3), TX = kFuseTX, TY = S::TY, NT = S::NT;
+  constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
+  extern __shared__ float lds[];
+  const long long ps = p.pstride;
+  const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, zc0 = blockIdx.z * kFuseZChunk;
+  const int zend = min(zc0 + kFuseZChunk, n2);
+  const int iters = zend - zc0 + 2;
+  for (int it = 0; it < iters; ++it) {
+    const int zp = zc0 - 1 + it;  // step-1 plane of this iteration
+    // ---- step 1 on the tile and its halo of plane zp
+    for (int r = threadIdx.x; r < R; r += NT) {
+      const int rx = r % RX, ry = r / RX;
+      int gx = x0 - 1 + rx, gy = y0 - 1 + ry, gz = zp;
+      if (gx < 0 || gx >= n0) {
+        if (p.bc[0] != 0) continue;
+        gx = fuse_wrap(gx, n0);
+      }
+      if (gy < 0 || gy >= n1) {
+        if (p.bc[1] != 0) continue;
+        gy = fuse_wrap(gy, n1);
+      }
+      if (gz < 0 || gz >= n2) {
+        if (p.bc[2] != 0) continue;
+        gz = fuse_wrap(gz, n2);
+      }
+      const int row = gz * n1 + gy;
+      RowInfo<D> ri;
+      row_setup<D>(p, row, ri);
+      col_setup<D>(p, gx, ri);
+      const int node = ri.rowbase + gx;
+      float f[Q];
+      if (ri.rowwall) {
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          f[k] = C[k * ps + node];
+        });
+      } else {
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr int cx = vel_comp(D, k, 0);
+          int idx = node + pull_offset<D, k>(ri);
+          if constexpr (cx != 0) {
+            if ((cx == 1) ? ri.lo[0] : ri.hi[0]) idx = p.xoff + row;
+          }
+          f[k] = A[k * ps + idx];
+        });
+        if (HALF && (ri.lo[0] || ri.hi[0])) {
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] -= A[opp_index(D, k) * ps + node];
+            }
+          });
+        }
+        collide_vals<D, float>(f, p);
+        // rows next to a wall of x_2 / x_3, owned by this block: kept for the
+        // step-2 wall kernel
+        const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
+                         y0 - 1 + ry < n1 && zp >= zc0 && zp < zend;
+        const bool near = (p.bc[1] != 0 && (ri.i[1] == 1 || ri.i[1] == n1 - 2)) ||
+                          (p.bc[2] != 0 && (ri.i[2] == 1 || ri.i[2] == n2 - 2));
+        if (own && near) {
+#pragma unroll
+          for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(f[k], C + k * ps + node);
+        }
+      }
+      static_for<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        lds[fuse_slot<HALF, k>(it) * R + r] = f[k];
+      });
+    }
+    __syncthreads();
+    // ---- step 2 on output plane zp - 1
+    if (it >= 2) {
+      const int gz = zp - 1;
+      for (int o = threadIdx.x; o < TX * TY; o += NT) {
+        const int ox = o % TX, oy = o / TX;
+        const int gx = x0 + ox, gy = y0 + oy;
+        if (gx >= n0 || gy >= n1) continue;
+        const int row = gz * n1 + gy;
+        RowInfo<D> ri;
+        row_setup<D>(p, row, ri);
+        if (ri.rowwall) continue;
+        col_setup<D>(p, gx, ri);
+        const int node = ri.rowbase + gx;
+        float f[Q];
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr Vec4i c = vel_vec(D, k);
+          constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
+          bool face = false;
+          if constexpr (c.v[0] != 0) face = (c.v[0] == 1) ? ri.lo[0] : ri.hi[0];
+          if (face) {
+            f[k] = B[k * ps + p.xoff + row];
+          } else {
+            const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
+            f[k] = lds[fuse_slot<HALF, k>(it - src_it) * R + rr];
+          }
+        });
+        if (HALF && (ri.lo[0] || ri.hi[0])) {
+          const int own = (oy + 1) * RX + (ox + 1);
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              constexpr int kb = opp_index(D, k);
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0])
+                f[k] -= lds[fuse_slot<HALF, kb>(it - 1) * R + own];
+            }
+          });
+        }
+        collide_store<D, float>(f, B, ps, node, p);
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // Many lattices in one launch (periodic instances): block b updates rows
@@ -994,6 +1183,63 @@ static hipError_t step_d(const KParams& p, int mode, const void* src, void* dst,
   if (p.wall_data)
     return step_dt<D, true>(p, mode, src, dst, phi_src, phi_dst, n, stream, ev);
   return step_dt<D, false>(p, mode, src, dst, phi_src, phi_dst, n, stream, ev);
+}
+
+template <bool TAN, bool HALF>
+static hipError_t fused_pair_t(const KParams& p, const float* A, float* B, float* C, long long n,
+                               hipStream_t stream, hipEvent_t* ev) {
+  using S = FuseShape<HALF>;
+  constexpr int R = (kFuseTX + 2) * (S::TY + 2);
+  constexpr size_t lds = sizeof(float) * S::SLOTS * R;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused2<HALF>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const LaunchShape s = step_shape(p);
+  const dim3 block(s.tx, s.ty);
+  const dim3 wgrid(static_cast<unsigned>((p.wall_rows + s.ty - 1) / s.ty));
+  const double t0 = static_cast<double>(n) * p.dt, t1 = static_cast<double>(n + 1) * p.dt;
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], stream);
+  };
+  if (p.bc[0] != 0) {
+    const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
+    hipLaunchKernelGGL((k_xface<3, float, TAN>), dim3(xb), dim3(256), 0, stream,
+                       const_cast<float*>(A), p, t0, static_cast<int>(kFP32));
+    hipLaunchKernelGGL((k_xface<3, float, TAN>), dim3(xb), dim3(256), 0, stream, B, p, t1,
+                       static_cast<int>(kFP32));
+  }
+  if (p.wall_rows > 0)
+    hipLaunchKernelGGL((k_wall<3, float, TAN>), wgrid, block, 0, stream, A, C, p, t0);
+  const dim3 grid(static_cast<unsigned>((p.n[0] + kFuseTX - 1) / kFuseTX),
+                  static_cast<unsigned>((p.n[1] + S::TY - 1) / S::TY),
+                  static_cast<unsigned>((p.n[2] + kFuseZChunk - 1) / kFuseZChunk));
+  mark(0);
+  hipLaunchKernelGGL((k_fused2<HALF>), grid, dim3(S::NT), lds, stream, A, B, C, p);
+  mark(1);
+  if (p.wall_rows > 0)
+    hipLaunchKernelGGL((k_wall<3, float, TAN>), wgrid, block, 0, stream, C, B, p, t1);
+  mark(2);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_pair(const KParams& p, const void* A, void* B, void* C, long long n,
+                             hipStream_t stream, hipEvent_t* ev) {
+  if (p.d != 3) return hipErrorInvalidValue;
+  auto* a = static_cast<const float*>(A);
+  auto* b = static_cast<float*>(B);
+  auto* c = static_cast<float*>(C);
+  const bool half = p.scheme == kHalfWay;
+  if (p.wall_data) {
+    return half ? fused_pair_t<true, true>(p, a, b, c, n, stream, ev)
+                : fused_pair_t<true, false>(p, a, b, c, n, stream, ev);
+  }
+  return half ? fused_pair_t<false, true>(p, a, b, c, n, stream, ev)
+              : fused_pair_t<false, false>(p, a, b, c, n, stream, ev);
 }
 
 hipError_t launch_step(const KParams& p, int mode, const void* src, void* dst,

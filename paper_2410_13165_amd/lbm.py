@@ -49,7 +49,7 @@ class LbmParams(C.Structure):
         ("bc", C.c_int32 * MAX_DIM), ("bc_order", C.c_int32), ("init_order", C.c_int32),
         ("precision", C.c_int32), ("field", C.POINTER(LbmField)),
         ("alloc", _ALLOC), ("free_fn", _FREE), ("alloc_ctx", C.c_void_p),
-        ("stream", C.c_void_p), ("wall_data", C.c_int32),
+        ("stream", C.c_void_p), ("wall_data", C.c_int32), ("steps_per_pass", C.c_int32),
     ]
 
 
@@ -60,7 +60,7 @@ class LbmInfo(C.Structure):
         ("dims", C.c_int64 * MAX_DIM), ("nodes", C.c_int64), ("step", C.c_int64),
         ("omega", C.c_double * MAX_Q), ("m4", C.c_double), ("min_omega", C.c_double),
         ("s", C.c_double), ("dt", C.c_double), ("phi_ref", C.c_double),
-        ("bytes_per_lu", C.c_int32), ("reserved", C.c_int32), ("pstride", C.c_int64),
+        ("bytes_per_lu", C.c_int32), ("steps_per_pass", C.c_int32), ("pstride", C.c_int64),
     ]
 
 
@@ -85,7 +85,7 @@ SIGNATURES = {
     "lbm_tape_end": (C.c_int, [C.c_void_p]),
     "lbm_profile_begin": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                  C.POINTER(C.c_int64)]),
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "lbm_batch_create": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double), C.POINTER(LbmParams),
                                    C.POINTER(C.c_void_p)]),
@@ -208,7 +208,8 @@ class Lattice:
                  u: Sequence[float], R: float = 0.0, origin: Optional[Sequence[float]] = None,
                  bc: Optional[Sequence[str]] = None, P: int = 4, K: int = 3,
                  precision: str = "fp64", field=None, g: float = 0.5,
-                 m4: Optional[float] = None, wall_data: str = "jets", device=None):
+                 m4: Optional[float] = None, wall_data: str = "jets",
+                 steps_per_pass: int = 2, device=None):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -238,6 +239,7 @@ class Lattice:
         p.precision = PRECISION[precision]
         self.precision = precision
         p.wall_data = WALL_DATA[wall_data]
+        p.steps_per_pass = int(steps_per_pass)
 
         self._field_keep = []
         if field is not None:
@@ -345,7 +347,7 @@ class Lattice:
             "dims": tuple(inf.dims[: inf.d]), "nodes": inf.nodes, "step": inf.step,
             "omega": np.array(inf.omega[: inf.q]), "m4": inf.m4, "min_omega": inf.min_omega,
             "s": inf.s, "dt": inf.dt, "phi_ref": inf.phi_ref, "bytes_per_lu": inf.bytes_per_lu,
-            "pstride": inf.pstride,
+            "pstride": inf.pstride, "steps_per_pass": inf.steps_per_pass,
         }
 
     def tape_begin(self, every: int):
@@ -384,9 +386,10 @@ class Lattice:
         return self
 
     def profile_end(self) -> dict:
-        b, w, n = C.c_double(), C.c_double(), C.c_int64()
-        self._check(self.lib.lbm_profile_end(self._h, C.byref(b), C.byref(w), C.byref(n)))
-        return {"bulk_ms": b.value, "wall_ms": w.value, "steps": n.value}
+        b, w, n, nl = C.c_double(), C.c_double(), C.c_int64(), C.c_int64()
+        self._check(self.lib.lbm_profile_end(self._h, C.byref(b), C.byref(w), C.byref(n),
+                                             C.byref(nl)))
+        return {"bulk_ms": b.value, "wall_ms": w.value, "steps": n.value, "launches": nl.value}
 
     def state_bytes(self) -> int:
         return int(self.lib.lbm_state_bytes(self._h))

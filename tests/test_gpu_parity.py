@@ -135,6 +135,59 @@ def test_tangential_wall_data_reduced_precision_and_lower_order(precision):
                 60, bc=["fullway"] * 3, precision=precision, wall_data="tangential")
 
 
+def _node_state(lat):
+    info = lat.info()
+    blob = lat.get_state().view(torch.float32).reshape(info["q"], info["pstride"])
+    return blob[:, : info["nodes"]].clone()
+
+
+@pytest.mark.parametrize("dims,bc,wall_data", [
+    ((67, 29, 23), ["periodic"] * 3, "jets"),
+    ((45, 30, 70), ["fullway"] * 3, "jets"),
+    ((44, 27, 66), ["halfway"] * 3, "jets"),
+    ((40, 18, 21), ["periodic", "fullway", "fullway"], "jets"),
+    ((40, 18, 21), ["fullway", "periodic", "fullway"], "jets"),
+    ((40, 18, 21), ["halfway", "halfway", "periodic"], "jets"),
+    ((70, 15, 9), ["fullway"] * 3, "tangential"),
+    ((3, 2, 5), ["fullway"] * 3, "jets"),
+    ((5, 4, 3), ["periodic"] * 3, "jets"),
+])
+def test_two_step_passes_equal_single_steps_bitwise(dims, bc, wall_data):
+    """float32, d = 3: steps taken two per bulk pass (intermediate state in LDS)
+    give bitwise the populations of single steps, for periodic, full-way,
+    half-way and mixed axes, ragged tiles and z-chunks, and odd step counts."""
+    spec = inputs.random_cosines(3, [0.05, -0.1, 0.08], 0.7, seed=71, kmax=1.0)
+    dx = 1.0 / max(dims[0] - 1, 1)
+    a = gpu_lattice(3, dims, dx, spec, bc=bc, precision="fp32", wall_data=wall_data)
+    from paper_2410_13165_amd import Lattice
+    b = Lattice(3, dims, 0.5, dx=dx, u=spec["u"], R=spec.get("R", 0.0), bc=bc, P=4, K=3,
+                precision="fp32", field=spec, wall_data=wall_data, steps_per_pass=1)
+    try:
+        assert a.info()["steps_per_pass"] == 2 and b.info()["steps_per_pass"] == 1
+        print(f"[fused] dims={dims} bc={bc} {wall_data}", flush=True)
+        for n in (2, 5, 14):
+            a.step(n)
+            b.step(n)
+            assert a.info()["step"] == b.info()["step"]
+            assert torch.equal(_node_state(a), _node_state(b)), n
+    finally:
+        a.close()
+        b.close()
+
+
+def test_two_step_profile_counts_passes():
+    spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0, seed=72, kmax=1.0)
+    lat = gpu_lattice(3, (40, 30, 20), 1.0 / 39, spec, bc=["fullway"] * 3, precision="fp32")
+    try:
+        lat.profile_begin(10)
+        lat.step(7)
+        prof = lat.profile_end()
+        assert prof["steps"] == 7 and prof["launches"] == 4
+        assert prof["bulk_ms"] > 0 and prof["wall_ms"] > 0
+    finally:
+        lat.close()
+
+
 def test_example1_source_term_fp32_reference():
     """R = 5 makes phi grow like R t; the float32 mode stores deviations from the
     uniform state omega (mean phi0 + R t) and must keep its accuracy."""
