@@ -315,7 +315,8 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   h->q = q_of(d);
   h->nodes = nodes;
   h->precision = p->precision;
-  h->steps_per_pass = (p->steps_per_pass == 2 && p->precision == LBM_FP32 && d == 3) ? 2 : 1;
+  h->steps_per_pass =
+      (p->steps_per_pass == 2 && p->precision != LBM_FP32_SPLIT && d == 3) ? 2 : 1;
   h->stream = static_cast<hipStream_t>(p->stream);
   h->alloc = p->alloc;
   h->free_fn = p->free_fn;
@@ -490,8 +491,8 @@ int lbm_step(lbm_handle* h, int64_t n) {
       h->prof_steps += todo;
     }
     hipError_t e = (todo == 2)
-                       ? launch_fused_pair(h->kp, h->buf[src], h->buf[dst], h->fuse_buf, h->step,
-                                           h->stream, ev)
+                       ? launch_fused_pair(h->kp, h->precision, h->buf[src], h->buf[dst],
+                                           h->fuse_buf, h->step, h->stream, ev)
                        : launch_step(h->kp, h->precision, h->buf[src], h->buf[dst],
                                      h->phib[src], h->phib[dst], h->step, h->stream, ev);
     if (e != hipSuccess) return hip_fail(h, e, "step kernel");

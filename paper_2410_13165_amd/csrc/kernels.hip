@@ -542,9 +542,10 @@ __global__ void __launch_bounds__(256)
 
 // ------------------------------------------------------ two fused steps --
 //
-// Two time steps t_n -> t_{n+2} in one pass (float32 storage, d = 3), so each
+// Two time steps t_n -> t_{n+2} in one pass (float32 or float64 storage,
+// d = 3), so each
 // stored population is read and written about once per two steps instead of
-// once per step.  A block owns an x_1-x_2 tile of kFuseTX x TY output nodes and
+// once per step.  A block owns an x_1-x_2 tile of TX x TY output nodes and
 // a chunk of x_3 planes, and marches along x_3: for step-1 plane z it updates
 // the tile plus a one-node halo (from A, the state at t_n) into LDS, then
 // updates output plane z - 1 of step 2 by pulling from the LDS planes z - 2,
@@ -560,17 +561,26 @@ __global__ void __launch_bounds__(256)
 // data of step 1 are in A's row slots and those of step 2 in B's (k_xface on
 // both before the launch).  Every node goes through exactly the arithmetic of
 // k_step, so the result is bitwise that of two single steps.
-constexpr int kFuseTX = 64;
+// Tiles fill most of the 160 KB of LDS with one block per CU: SLOTS planes of
+// (TX + 2) (TY + 2) values; a row of a tile is 256 B of one population plane.
 constexpr int kFuseZChunk = 64;
-template <bool HALF>
+template <class T, bool HALF>
 struct FuseShape;
 template <>
-struct FuseShape<false> {
-  static constexpr int TY = 13, NT = 1024, SLOTS = 38;
+struct FuseShape<float, false> {
+  static constexpr int TX = 64, TY = 13, NT = 1024, SLOTS = 38;
 };
 template <>
-struct FuseShape<true> {
-  static constexpr int TY = 11, NT = 896, SLOTS = 43;
+struct FuseShape<float, true> {
+  static constexpr int TX = 64, TY = 11, NT = 896, SLOTS = 43;
+};
+template <>
+struct FuseShape<double, false> {
+  static constexpr int TX = 32, TY = 12, NT = 512, SLOTS = 38;
+};
+template <>
+struct FuseShape<double, true> {
+  static constexpr int TX = 32, TY = 12, NT = 512, SLOTS = 43;
 };
 
 // index of population k among those with the same c_3
@@ -598,14 +608,14 @@ __device__ __forceinline__ int fuse_wrap(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-template <bool HALF>
-__global__ void __launch_bounds__(FuseShape<HALF>::NT)
-    k_fused2(const float* __restrict__ A, float* __restrict__ B, float* __restrict__ C,
-             const KParams p) {
-  using S = FuseShape<HALF>;
-  constexpr int D = 3, Q = q_of(3), TX = kFuseTX, TY = S::TY, NT = S::NT;
+template <class T, bool HALF>
+__global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
+    k_fused2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p) {
+  using S = FuseShape<T, HALF>;
+  constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
   constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
-  extern __shared__ float lds[];
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  T* lds = reinterpret_cast<T*>(fuse_lds);
   const long long ps = p.pstride;
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, zc0 = blockIdx.z * kFuseZChunk;
@@ -634,7 +644,7 @@ __global__ void __launch_bounds__(FuseShape<HALF>::NT)
       row_setup<D>(p, row, ri);
       col_setup<D>(p, gx, ri);
       const int node = ri.rowbase + gx;
-      float f[Q];
+      T f[Q];
       if (ri.rowwall) {
         static_for<0, Q>([&](auto K) {
           constexpr int k = decltype(K)::value;
@@ -659,7 +669,7 @@ __global__ void __launch_bounds__(FuseShape<HALF>::NT)
             }
           });
         }
-        collide_vals<D, float>(f, p);
+        collide_vals<D, T>(f, p);
         // rows next to a wall of x_2 / x_3, owned by this block: kept for the
         // step-2 wall kernel
         const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
@@ -690,7 +700,7 @@ __global__ void __launch_bounds__(FuseShape<HALF>::NT)
         if (ri.rowwall) continue;
         col_setup<D>(p, gx, ri);
         const int node = ri.rowbase + gx;
-        float f[Q];
+        T f[Q];
         static_for<0, Q>([&](auto K) {
           constexpr int k = decltype(K)::value;
           constexpr Vec4i c = vel_vec(D, k);
@@ -716,7 +726,7 @@ __global__ void __launch_bounds__(FuseShape<HALF>::NT)
             }
           });
         }
-        collide_store<D, float>(f, B, ps, node, p);
+        collide_store<D, T>(f, B, ps, node, p);
       }
     }
     __syncthreads();
@@ -1185,15 +1195,17 @@ static hipError_t step_d(const KParams& p, int mode, const void* src, void* dst,
   return step_dt<D, false>(p, mode, src, dst, phi_src, phi_dst, n, stream, ev);
 }
 
-template <bool TAN, bool HALF>
-static hipError_t fused_pair_t(const KParams& p, const float* A, float* B, float* C, long long n,
+template <class T, bool TAN, bool HALF>
+static hipError_t fused_pair_t(const KParams& p, const T* A, T* B, T* C, long long n,
                                hipStream_t stream, hipEvent_t* ev) {
-  using S = FuseShape<HALF>;
-  constexpr int R = (kFuseTX + 2) * (S::TY + 2);
-  constexpr size_t lds = sizeof(float) * S::SLOTS * R;
+  using S = FuseShape<T, HALF>;
+  constexpr int R = (S::TX + 2) * (S::TY + 2);
+  constexpr size_t lds = sizeof(T) * S::SLOTS * R;
+  static_assert(lds <= 160 * 1024, "fused tile exceeds the LDS of a CU");
+  constexpr int mode = std::is_same<T, float>::value ? kFP32 : kFP64;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused2<HALF>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused2<T, HALF>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -1208,38 +1220,45 @@ static hipError_t fused_pair_t(const KParams& p, const float* A, float* B, float
   };
   if (p.bc[0] != 0) {
     const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
-    hipLaunchKernelGGL((k_xface<3, float, TAN>), dim3(xb), dim3(256), 0, stream,
-                       const_cast<float*>(A), p, t0, static_cast<int>(kFP32));
-    hipLaunchKernelGGL((k_xface<3, float, TAN>), dim3(xb), dim3(256), 0, stream, B, p, t1,
-                       static_cast<int>(kFP32));
+    hipLaunchKernelGGL((k_xface<3, T, TAN>), dim3(xb), dim3(256), 0, stream, const_cast<T*>(A),
+                       p, t0, mode);
+    hipLaunchKernelGGL((k_xface<3, T, TAN>), dim3(xb), dim3(256), 0, stream, B, p, t1, mode);
   }
   if (p.wall_rows > 0)
-    hipLaunchKernelGGL((k_wall<3, float, TAN>), wgrid, block, 0, stream, A, C, p, t0);
-  const dim3 grid(static_cast<unsigned>((p.n[0] + kFuseTX - 1) / kFuseTX),
+    hipLaunchKernelGGL((k_wall<3, T, TAN>), wgrid, block, 0, stream, A, C, p, t0);
+  const dim3 grid(static_cast<unsigned>((p.n[0] + S::TX - 1) / S::TX),
                   static_cast<unsigned>((p.n[1] + S::TY - 1) / S::TY),
                   static_cast<unsigned>((p.n[2] + kFuseZChunk - 1) / kFuseZChunk));
   mark(0);
-  hipLaunchKernelGGL((k_fused2<HALF>), grid, dim3(S::NT), lds, stream, A, B, C, p);
+  hipLaunchKernelGGL((k_fused2<T, HALF>), grid, dim3(S::NT), lds, stream, A, B, C, p);
   mark(1);
   if (p.wall_rows > 0)
-    hipLaunchKernelGGL((k_wall<3, float, TAN>), wgrid, block, 0, stream, C, B, p, t1);
+    hipLaunchKernelGGL((k_wall<3, T, TAN>), wgrid, block, 0, stream, C, B, p, t1);
   mark(2);
   return hipGetLastError();
 }
 
-hipError_t launch_fused_pair(const KParams& p, const void* A, void* B, void* C, long long n,
-                             hipStream_t stream, hipEvent_t* ev) {
-  if (p.d != 3) return hipErrorInvalidValue;
-  auto* a = static_cast<const float*>(A);
-  auto* b = static_cast<float*>(B);
-  auto* c = static_cast<float*>(C);
+template <class T>
+static hipError_t fused_pair_m(const KParams& p, const void* A, void* B, void* C, long long n,
+                               hipStream_t stream, hipEvent_t* ev) {
+  auto* a = static_cast<const T*>(A);
+  auto* b = static_cast<T*>(B);
+  auto* c = static_cast<T*>(C);
   const bool half = p.scheme == kHalfWay;
   if (p.wall_data) {
-    return half ? fused_pair_t<true, true>(p, a, b, c, n, stream, ev)
-                : fused_pair_t<true, false>(p, a, b, c, n, stream, ev);
+    return half ? fused_pair_t<T, true, true>(p, a, b, c, n, stream, ev)
+                : fused_pair_t<T, true, false>(p, a, b, c, n, stream, ev);
   }
-  return half ? fused_pair_t<false, true>(p, a, b, c, n, stream, ev)
-              : fused_pair_t<false, false>(p, a, b, c, n, stream, ev);
+  return half ? fused_pair_t<T, false, true>(p, a, b, c, n, stream, ev)
+              : fused_pair_t<T, false, false>(p, a, b, c, n, stream, ev);
+}
+
+hipError_t launch_fused_pair(const KParams& p, int mode, const void* A, void* B, void* C,
+                             long long n, hipStream_t stream, hipEvent_t* ev) {
+  if (p.d != 3) return hipErrorInvalidValue;
+  if (mode == kFP32) return fused_pair_m<float>(p, A, B, C, n, stream, ev);
+  if (mode == kFP64) return fused_pair_m<double>(p, A, B, C, n, stream, ev);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_step(const KParams& p, int mode, const void* src, void* dst,

@@ -137,7 +137,8 @@ def test_tangential_wall_data_reduced_precision_and_lower_order(precision):
 
 def _node_state(lat):
     info = lat.info()
-    blob = lat.get_state().view(torch.float32).reshape(info["q"], info["pstride"])
+    dt = torch.float64 if lat.precision == "fp64" else torch.float32
+    blob = lat.get_state().view(dt).reshape(info["q"], info["pstride"])
     return blob[:, : info["nodes"]].clone()
 
 
@@ -152,19 +153,20 @@ def _node_state(lat):
     ((3, 2, 5), ["fullway"] * 3, "jets"),
     ((5, 4, 3), ["periodic"] * 3, "jets"),
 ])
-def test_two_step_passes_equal_single_steps_bitwise(dims, bc, wall_data):
-    """float32, d = 3: steps taken two per bulk pass (intermediate state in LDS)
-    give bitwise the populations of single steps, for periodic, full-way,
-    half-way and mixed axes, ragged tiles and z-chunks, and odd step counts."""
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_two_step_passes_equal_single_steps_bitwise(dims, bc, wall_data, precision):
+    """d = 3: steps taken two per bulk pass (intermediate state in LDS) give
+    bitwise the populations of single steps, for periodic, full-way, half-way
+    and mixed axes, ragged tiles and z-chunks, and odd step counts."""
     spec = inputs.random_cosines(3, [0.05, -0.1, 0.08], 0.7, seed=71, kmax=1.0)
     dx = 1.0 / max(dims[0] - 1, 1)
-    a = gpu_lattice(3, dims, dx, spec, bc=bc, precision="fp32", wall_data=wall_data)
+    a = gpu_lattice(3, dims, dx, spec, bc=bc, precision=precision, wall_data=wall_data)
     from paper_2410_13165_amd import Lattice
     b = Lattice(3, dims, 0.5, dx=dx, u=spec["u"], R=spec.get("R", 0.0), bc=bc, P=4, K=3,
-                precision="fp32", field=spec, wall_data=wall_data, steps_per_pass=1)
+                precision=precision, field=spec, wall_data=wall_data, steps_per_pass=1)
     try:
         assert a.info()["steps_per_pass"] == 2 and b.info()["steps_per_pass"] == 1
-        print(f"[fused] dims={dims} bc={bc} {wall_data}", flush=True)
+        print(f"[fused] dims={dims} bc={bc} {wall_data} {precision}", flush=True)
         for n in (2, 5, 14):
             a.step(n)
             b.step(n)
