@@ -51,7 +51,8 @@ struct lbm_handle {
   bool profiling = false;
   // two steps per bulk pass (float32, d = 3): scratch state for the wall rows
   int steps_per_pass = 1;
-  void* fuse_buf = nullptr;
+  void* fuse_buf = nullptr;     // state_bytes: populations (+ phi in split mode)
+  double* xdata2 = nullptr;     // split mode: x_1-face data of the second step
 };
 
 static thread_local std::string g_create_error;
@@ -105,9 +106,11 @@ void release(lbm_handle* h) {
   dev_free(h, h->result);
   dev_free(h, h->kp.xdata);
   dev_free(h, h->fuse_buf);
+  dev_free(h, h->xdata2);
   h->partial = h->result = nullptr;
   h->kp.xdata = nullptr;
   h->fuse_buf = nullptr;
+  h->xdata2 = nullptr;
 }
 
 // Copy the analytic field into the kernel parameter block.
@@ -315,8 +318,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   h->q = q_of(d);
   h->nodes = nodes;
   h->precision = p->precision;
-  h->steps_per_pass =
-      (p->steps_per_pass == 2 && p->precision != LBM_FP32_SPLIT && d == 3) ? 2 : 1;
+  h->steps_per_pass = (p->steps_per_pass == 2 && d == 3) ? 2 : 1;
   h->stream = static_cast<hipStream_t>(p->stream);
   h->alloc = p->alloc;
   h->free_fn = p->free_fn;
@@ -477,8 +479,12 @@ int lbm_step(lbm_handle* h, int64_t n) {
   // tape records checkpoints, which fall on single steps)
   const bool pairs = h->steps_per_pass == 2 && !h->tape_active;
   if (pairs && n >= 2 && !h->fuse_buf) {
-    h->fuse_buf = dev_alloc(h, pop_bytes(h));
+    h->fuse_buf = dev_alloc(h, state_bytes(h));
     if (!h->fuse_buf) return fail(h, LBM_ENOMEM, "scratch state for two-step passes");
+    if (xdata_bytes(h) > 0) {
+      h->xdata2 = static_cast<double*>(dev_alloc(h, xdata_bytes(h)));
+      if (!h->xdata2) return fail(h, LBM_ENOMEM, "x-face data for two-step passes");
+    }
   }
   int64_t i = 0;
   while (i < n) {
@@ -490,11 +496,15 @@ int lbm_step(lbm_handle* h, int64_t n) {
       ++h->prof_used;
       h->prof_steps += todo;
     }
-    hipError_t e = (todo == 2)
-                       ? launch_fused_pair(h->kp, h->precision, h->buf[src], h->buf[dst],
-                                           h->fuse_buf, h->step, h->stream, ev)
-                       : launch_step(h->kp, h->precision, h->buf[src], h->buf[dst],
-                                     h->phib[src], h->phib[dst], h->step, h->stream, ev);
+    hipError_t e;
+    if (todo == 2) {
+      const FusedBufs fb{h->buf[src], h->buf[dst], h->fuse_buf, h->phib[src], h->phib[dst],
+                         blob_phi(h, h->fuse_buf), h->xdata2};
+      e = launch_fused_pair(h->kp, h->precision, fb, h->step, h->stream, ev);
+    } else {
+      e = launch_step(h->kp, h->precision, h->buf[src], h->buf[dst], h->phib[src],
+                      h->phib[dst], h->step, h->stream, ev);
+    }
     if (e != hipSuccess) return hip_fail(h, e, "step kernel");
     h->cur = dst;
     h->step += todo;

@@ -94,14 +94,26 @@ hipError_t launch_step(const KParams& p, int mode, const void* src, void* dst,
                        const double* phi_src, double* phi_dst, long long n,
                        hipStream_t stream, hipEvent_t* ev = nullptr);
 
-// Two steps t_n -> t_{n+2} of a float32 or float64 lattice (mode kFP32 /
-// kFP64) with d = 3 in one pass of the bulk kernel (k_fused2): A holds the
-// state at t_n, B receives t_{n+2}, C is a scratch state buffer of the same
-// size for the rows on and next to the walls of x_2 / x_3.  Bitwise equal to
-// two launch_step calls.  ev (nullable): three events around the fused kernel
-// and after the step-2 wall kernel.
-hipError_t launch_fused_pair(const KParams& p, int mode, const void* A, void* B, void* C,
-                             long long n, hipStream_t stream, hipEvent_t* ev = nullptr);
+// Buffers of a two-step pass: A holds the state at t_n, B receives t_{n+2},
+// C is a scratch state of the same layout for the rows on and next to the
+// walls of x_2 / x_3.  Split mode adds the phi planes and a second x_1-face
+// array (the step-2 data; p.xdata holds step 1's).
+struct FusedBufs {
+  const void* A;
+  void* B;
+  void* C;
+  const double* phiA;
+  double* phiB;
+  double* phiC;
+  double* xdata2;
+};
+
+// Two steps t_n -> t_{n+2} of a lattice with d = 3 (any mode) in one pass of
+// the bulk kernel (k_fused2, k_fused2_split).  Bitwise equal to two
+// launch_step calls.  ev (nullable): three events around the fused kernel and
+// after the step-2 wall kernel.
+hipError_t launch_fused_pair(const KParams& p, int mode, const FusedBufs& fb, long long n,
+                             hipStream_t stream, hipEvent_t* ev = nullptr);
 
 // Initial state from the analytic field (phi0 == nullptr) or from device
 // arrays (grad0 == nullptr: fourth-order central differences).

@@ -823,6 +823,161 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Two fused steps of the split representation (d = 3), organised as k_fused2:
+// the LDS keeps the step-1 g_k (float32, the same plane slots) and phi
+// (float64, a ring of three planes).  The x_1-face data of step 2 come from a
+// second x-face array (xd2); rows on and next to the walls of x_2 / x_3 go
+// through the scratch state (gC, phiC) as in k_fused2.
+template <bool HALF>
+struct FuseSplitShape;
+template <>
+struct FuseSplitShape<false> {
+  static constexpr int TX = 64, TY = 11, NT = 1024, SLOTS = 38;
+};
+template <>
+struct FuseSplitShape<true> {
+  static constexpr int TX = 64, TY = 10, NT = 1024, SLOTS = 43;
+};
+
+template <bool HALF>
+__global__ void __launch_bounds__(1024)
+    k_fused2_split(const float* __restrict__ gA, float* __restrict__ gB, float* __restrict__ gC,
+                   const double* __restrict__ phiA, double* __restrict__ phiB,
+                   double* __restrict__ phiC, const KParams p, const double* __restrict__ xd2) {
+  using S = FuseSplitShape<HALF>;
+  constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
+  constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
+  constexpr int SX = 2 * D - 1;
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  float* lg = reinterpret_cast<float*>(fuse_lds);
+  double* lphi = reinterpret_cast<double*>(fuse_lds + sizeof(float) * S::SLOTS * R);
+  const long long ps = p.pstride;
+  const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, zc0 = blockIdx.z * kFuseZChunk;
+  const int zend = min(zc0 + kFuseZChunk, n2);
+  const int iters = zend - zc0 + 2;
+  const double oms = 1.0 - p.s;
+  const double dtR = p.dt * p.R;
+  for (int it = 0; it < iters; ++it) {
+    const int zp = zc0 - 1 + it;
+    for (int r = threadIdx.x; r < R; r += NT) {
+      const int rx = r % RX, ry = r / RX;
+      int gx = x0 - 1 + rx, gy = y0 - 1 + ry, gz = zp;
+      if (gx < 0 || gx >= n0) {
+        if (p.bc[0] != 0) continue;
+        gx = fuse_wrap(gx, n0);
+      }
+      if (gy < 0 || gy >= n1) {
+        if (p.bc[1] != 0) continue;
+        gy = fuse_wrap(gy, n1);
+      }
+      if (gz < 0 || gz >= n2) {
+        if (p.bc[2] != 0) continue;
+        gz = fuse_wrap(gz, n2);
+      }
+      const int row = gz * n1 + gy;
+      RowInfo<D> ri;
+      row_setup<D>(p, row, ri);
+      col_setup<D>(p, gx, ri);
+      const int node = ri.rowbase + gx;
+      float g[Q];
+      double phi;
+      if (ri.rowwall) {
+        phi = phiC[node];
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          g[k] = gC[k * ps + node];
+        });
+      } else {
+        double f[Q];
+        split_pull<D>(f, gA, phiA, ps, node, ri, p);
+        if (ri.lo[0] || ri.hi[0]) {
+          const double* W = p.xdata + (ri.hi[0] ? SX * p.rows : 0) + row;
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                double v = W[(long long)xface_slot(D, k) * p.rows];
+                if (HALF) v -= split_fstar<D>(gA, phiA, ps, node, opp_index(D, k), p);
+                f[k] = v;
+              }
+            }
+          });
+        }
+        // split_store's arithmetic, into registers
+        phi = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) phi += f[k];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) g[k] = static_cast<float>(f[k] - p.omega[k] * phi);
+        const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
+                         y0 - 1 + ry < n1 && zp >= zc0 && zp < zend;
+        const bool near = (p.bc[1] != 0 && (ri.i[1] == 1 || ri.i[1] == n1 - 2)) ||
+                          (p.bc[2] != 0 && (ri.i[2] == 1 || ri.i[2] == n2 - 2));
+        if (own && near) {
+          __builtin_nontemporal_store(phi, phiC + node);
+#pragma unroll
+          for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(g[k], gC + k * ps + node);
+        }
+      }
+      static_for<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        lg[fuse_slot<HALF, k>(it) * R + r] = g[k];
+      });
+      lphi[(it % 3) * R + r] = phi;
+    }
+    __syncthreads();
+    if (it >= 2) {
+      const int gz = zp - 1;
+      for (int o = threadIdx.x; o < TX * TY; o += NT) {
+        const int ox = o % TX, oy = o / TX;
+        const int gx = x0 + ox, gy = y0 + oy;
+        if (gx >= n0 || gy >= n1) continue;
+        const int row = gz * n1 + gy;
+        RowInfo<D> ri;
+        row_setup<D>(p, row, ri);
+        if (ri.rowwall) continue;
+        col_setup<D>(p, gx, ri);
+        const int node = ri.rowbase + gx;
+        double f[Q];
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr Vec4i c = vel_vec(D, k);
+          constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
+          const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
+          const double ph = lphi[((it - src_it) % 3) * R + rr];
+          const float gk = lg[fuse_slot<HALF, k>(it - src_it) * R + rr];
+          f[k] = fma(p.omega[k], ph, fma(oms, static_cast<double>(gk), dtR * p.omega[k]));
+        });
+        if (ri.lo[0] || ri.hi[0]) {
+          const double* W = xd2 + (ri.hi[0] ? SX * p.rows : 0) + row;
+          const int own = (oy + 1) * RX + (ox + 1);
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                double v = W[(long long)xface_slot(D, k) * p.rows];
+                if constexpr (HALF) {
+                  constexpr int kb = opp_index(D, k);
+                  const double ph = lphi[((it - 1) % 3) * R + own];
+                  const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
+                  v -= fma(p.omega[kb], ph,
+                           fma(1.0 - p.s, static_cast<double>(gb), p.dt * p.R * p.omega[kb]));
+                }
+                f[k] = v;
+              }
+            }
+          });
+        }
+        split_store<D>(f, gB, phiB, ps, node, p);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Rows on a wall of an axis >= 2.  Face (a, side), a >= 2, lists the rows
 // with i_a at that side whose indices on the Dirichlet axes 2 <= b < a are
 // interior, so every wall row is visited once; threads run along x_1 as in the
@@ -1238,12 +1393,66 @@ static hipError_t fused_pair_t(const KParams& p, const T* A, T* B, T* C, long lo
   return hipGetLastError();
 }
 
+template <bool TAN, bool HALF>
+static hipError_t fused_pair_split(const KParams& p, const FusedBufs& fb, long long n,
+                                   hipStream_t stream, hipEvent_t* ev) {
+  using S = FuseSplitShape<HALF>;
+  constexpr int R = (S::TX + 2) * (S::TY + 2);
+  constexpr size_t lds = sizeof(float) * S::SLOTS * R + sizeof(double) * 3 * R;
+  static_assert(lds <= 160 * 1024, "fused tile exceeds the LDS of a CU");
+  static_assert((sizeof(float) * S::SLOTS * R) % 8 == 0, "phi planes must be 8-byte aligned");
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused2_split<HALF>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  auto* gA = static_cast<const float*>(fb.A);
+  auto* gB = static_cast<float*>(fb.B);
+  auto* gC = static_cast<float*>(fb.C);
+  const LaunchShape s = step_shape(p);
+  const dim3 block(s.tx, s.ty);
+  const dim3 wgrid(static_cast<unsigned>((p.wall_rows + s.ty - 1) / s.ty));
+  const double t0 = static_cast<double>(n) * p.dt, t1 = static_cast<double>(n + 1) * p.dt;
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], stream);
+  };
+  if (p.bc[0] != 0) {
+    // the x_1-face data of the split mode live in p.xdata; the second step's
+    // go to the second array
+    KParams p2 = p;
+    p2.xdata = fb.xdata2;
+    const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
+    hipLaunchKernelGGL((k_xface<3, float, TAN>), dim3(xb), dim3(256), 0, stream,
+                       const_cast<float*>(gA), p, t0, static_cast<int>(kSplit));
+    hipLaunchKernelGGL((k_xface<3, float, TAN>), dim3(xb), dim3(256), 0, stream, gB, p2, t1,
+                       static_cast<int>(kSplit));
+  }
+  if (p.wall_rows > 0)
+    hipLaunchKernelGGL((k_wall_split<3, TAN>), wgrid, block, 0, stream, gA, gC, fb.phiA, fb.phiC,
+                       p, t0);
+  const dim3 grid(static_cast<unsigned>((p.n[0] + S::TX - 1) / S::TX),
+                  static_cast<unsigned>((p.n[1] + S::TY - 1) / S::TY),
+                  static_cast<unsigned>((p.n[2] + kFuseZChunk - 1) / kFuseZChunk));
+  mark(0);
+  hipLaunchKernelGGL((k_fused2_split<HALF>), grid, dim3(S::NT), lds, stream, gA, gB, gC, fb.phiA,
+                     fb.phiB, fb.phiC, p, static_cast<const double*>(fb.xdata2));
+  mark(1);
+  if (p.wall_rows > 0)
+    hipLaunchKernelGGL((k_wall_split<3, TAN>), wgrid, block, 0, stream, gC, gB, fb.phiC, fb.phiB,
+                       p, t1);
+  mark(2);
+  return hipGetLastError();
+}
+
 template <class T>
-static hipError_t fused_pair_m(const KParams& p, const void* A, void* B, void* C, long long n,
+static hipError_t fused_pair_m(const KParams& p, const FusedBufs& fb, long long n,
                                hipStream_t stream, hipEvent_t* ev) {
-  auto* a = static_cast<const T*>(A);
-  auto* b = static_cast<T*>(B);
-  auto* c = static_cast<T*>(C);
+  auto* a = static_cast<const T*>(fb.A);
+  auto* b = static_cast<T*>(fb.B);
+  auto* c = static_cast<T*>(fb.C);
   const bool half = p.scheme == kHalfWay;
   if (p.wall_data) {
     return half ? fused_pair_t<T, true, true>(p, a, b, c, n, stream, ev)
@@ -1253,11 +1462,20 @@ static hipError_t fused_pair_m(const KParams& p, const void* A, void* B, void* C
               : fused_pair_t<T, false, false>(p, a, b, c, n, stream, ev);
 }
 
-hipError_t launch_fused_pair(const KParams& p, int mode, const void* A, void* B, void* C,
-                             long long n, hipStream_t stream, hipEvent_t* ev) {
+hipError_t launch_fused_pair(const KParams& p, int mode, const FusedBufs& fb, long long n,
+                             hipStream_t stream, hipEvent_t* ev) {
   if (p.d != 3) return hipErrorInvalidValue;
-  if (mode == kFP32) return fused_pair_m<float>(p, A, B, C, n, stream, ev);
-  if (mode == kFP64) return fused_pair_m<double>(p, A, B, C, n, stream, ev);
+  if (mode == kFP32) return fused_pair_m<float>(p, fb, n, stream, ev);
+  if (mode == kFP64) return fused_pair_m<double>(p, fb, n, stream, ev);
+  if (mode == kSplit) {
+    if (p.bc[0] != 0 && !fb.xdata2) return hipErrorInvalidValue;
+    const bool half = p.scheme == kHalfWay;
+    if (p.wall_data)
+      return half ? fused_pair_split<true, true>(p, fb, n, stream, ev)
+                  : fused_pair_split<true, false>(p, fb, n, stream, ev);
+    return half ? fused_pair_split<false, true>(p, fb, n, stream, ev)
+                : fused_pair_split<false, false>(p, fb, n, stream, ev);
+  }
   return hipErrorInvalidValue;
 }
 

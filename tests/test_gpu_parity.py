@@ -136,10 +136,19 @@ def test_tangential_wall_data_reduced_precision_and_lower_order(precision):
 
 
 def _node_state(lat):
+    """Populations (split mode: g_k and phi) of the nodes, without the padding
+    and x_1-face slots of the state blob."""
     info = lat.info()
-    dt = torch.float64 if lat.precision == "fp64" else torch.float32
-    blob = lat.get_state().view(dt).reshape(info["q"], info["pstride"])
-    return blob[:, : info["nodes"]].clone()
+    q, ps, nodes = info["q"], info["pstride"], info["nodes"]
+    blob = lat.get_state()
+    if lat.precision == "fp64":
+        return blob.view(torch.float64).reshape(q, ps)[:, :nodes].clone()
+    pop = blob[: q * ps * 4].view(torch.float32).reshape(q, ps)[:, :nodes]
+    if lat.precision == "fp32":
+        return pop.clone()
+    phi = blob[q * ps * 4:].view(torch.float64)[:nodes]
+    return torch.cat([pop.reshape(-1).view(torch.int32).to(torch.int64),
+                      phi.view(torch.int64)])
 
 
 @pytest.mark.parametrize("dims,bc,wall_data", [
@@ -153,7 +162,7 @@ def _node_state(lat):
     ((3, 2, 5), ["fullway"] * 3, "jets"),
     ((5, 4, 3), ["periodic"] * 3, "jets"),
 ])
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32_split"])
 def test_two_step_passes_equal_single_steps_bitwise(dims, bc, wall_data, precision):
     """d = 3: steps taken two per bulk pass (intermediate state in LDS) give
     bitwise the populations of single steps, for periodic, full-way, half-way
