@@ -546,7 +546,7 @@ __global__ void __launch_bounds__(256)
 // d = 3), so each
 // stored population is read and written about once per two steps instead of
 // once per step.  A block owns an x_1-x_2 tile of TX x TY output nodes and
-// a chunk of x_3 planes, and marches along x_3: for step-1 plane z it updates
+// a chunk of x_3 planes (fuse_tile), and marches along x_3: for step-1 plane z it updates
 // the tile plus a one-node halo (from A, the state at t_n) into LDS, then
 // updates output plane z - 1 of step 2 by pulling from the LDS planes z - 2,
 // z - 1 and z, and stores it to B.  Each plane's step-1 values stay in LDS only
@@ -608,6 +608,23 @@ __device__ __forceinline__ int fuse_wrap(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// Tile of this block.  Workgroups go to the 8 XCDs round-robin by index, so
+// block b is given tile (b mod 8) * per + b / 8: each XCD walks a contiguous
+// run of tiles in x_1-fastest order, and the tiles next to each other in x_1
+// and x_2, whose halos read the same cache lines, run at the same time under
+// one L2.
+__device__ __forceinline__ void fuse_tile(const KParams& p, int TX, int TY, int& bx, int& by,
+                                          int& bz) {
+  const int gx = (p.n[0] + TX - 1) / TX, gy = (p.n[1] + TY - 1) / TY;
+  const int nb = static_cast<int>(gridDim.x);
+  const int per = nb / 8;
+  const int b = static_cast<int>(blockIdx.x);
+  const int t = (b < 8 * per) ? (b % 8) * per + b / 8 : b;
+  bx = t % gx;
+  by = (t / gx) % gy;
+  bz = t / (gx * gy);
+}
+
 template <class T, bool HALF>
 __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
     k_fused2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p) {
@@ -618,7 +635,9 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
   T* lds = reinterpret_cast<T*>(fuse_lds);
   const long long ps = p.pstride;
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, zc0 = blockIdx.z * kFuseZChunk;
+  int tx_, ty_, tz_;
+  fuse_tile(p, TX, TY, tx_, ty_, tz_);
+  const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * kFuseZChunk;
   const int zend = min(zc0 + kFuseZChunk, n2);
   const int iters = zend - zc0 + 2;
   for (int it = 0; it < iters; ++it) {
@@ -853,7 +872,9 @@ __global__ void __launch_bounds__(1024)
   double* lphi = reinterpret_cast<double*>(fuse_lds + sizeof(float) * S::SLOTS * R);
   const long long ps = p.pstride;
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, zc0 = blockIdx.z * kFuseZChunk;
+  int tx_, ty_, tz_;
+  fuse_tile(p, TX, TY, tx_, ty_, tz_);
+  const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * kFuseZChunk;
   const int zend = min(zc0 + kFuseZChunk, n2);
   const int iters = zend - zc0 + 2;
   const double oms = 1.0 - p.s;
@@ -1381,9 +1402,9 @@ static hipError_t fused_pair_t(const KParams& p, const T* A, T* B, T* C, long lo
   }
   if (p.wall_rows > 0)
     hipLaunchKernelGGL((k_wall<3, T, TAN>), wgrid, block, 0, stream, A, C, p, t0);
-  const dim3 grid(static_cast<unsigned>((p.n[0] + S::TX - 1) / S::TX),
-                  static_cast<unsigned>((p.n[1] + S::TY - 1) / S::TY),
-                  static_cast<unsigned>((p.n[2] + kFuseZChunk - 1) / kFuseZChunk));
+  const dim3 grid(static_cast<unsigned>(((p.n[0] + S::TX - 1) / S::TX) *
+                                        ((p.n[1] + S::TY - 1) / S::TY) *
+                                        ((p.n[2] + kFuseZChunk - 1) / kFuseZChunk)));
   mark(0);
   hipLaunchKernelGGL((k_fused2<T, HALF>), grid, dim3(S::NT), lds, stream, A, B, C, p);
   mark(1);
@@ -1433,9 +1454,9 @@ static hipError_t fused_pair_split(const KParams& p, const FusedBufs& fb, long l
   if (p.wall_rows > 0)
     hipLaunchKernelGGL((k_wall_split<3, TAN>), wgrid, block, 0, stream, gA, gC, fb.phiA, fb.phiC,
                        p, t0);
-  const dim3 grid(static_cast<unsigned>((p.n[0] + S::TX - 1) / S::TX),
-                  static_cast<unsigned>((p.n[1] + S::TY - 1) / S::TY),
-                  static_cast<unsigned>((p.n[2] + kFuseZChunk - 1) / kFuseZChunk));
+  const dim3 grid(static_cast<unsigned>(((p.n[0] + S::TX - 1) / S::TX) *
+                                        ((p.n[1] + S::TY - 1) / S::TY) *
+                                        ((p.n[2] + kFuseZChunk - 1) / kFuseZChunk)));
   mark(0);
   hipLaunchKernelGGL((k_fused2_split<HALF>), grid, dim3(S::NT), lds, stream, gA, gB, gC, fb.phiA,
                      fb.phiB, fb.phiC, p, static_cast<const double*>(fb.xdata2));
