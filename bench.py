@@ -152,11 +152,20 @@ def run_adjoint(precision: str = "fp32", n=None, steps=None):
         t4 = time.perf_counter()
         gnorm = float(g["phi0"].norm())
         lat.tape_end()
+        # the same forward without recording checkpoints
+        lat.set_initial(phi0)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        t6 = time.perf_counter()
     finally:
         lat.close()
         torch.cuda.empty_cache()
     fwd = t1 - t0
     return {
+        "forward_untaped_s": t6 - t5,
+        "ratio_vs_untaped_forward": (t3 - t2) / (t6 - t5),
         "workload": (f"D3Q19 {n}^3 periodic, {precision}, {steps} steps, checkpoints every "
                      f"{w['every']}, Gaussian random fields (corr {w['corr']})"),
         "forward_s": fwd,

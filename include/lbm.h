@@ -187,7 +187,8 @@ int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_ph
    the wall schemes applied inline.  With steps_per_pass = 2 (d = 3)
    the steps go in pairs through one bulk pass that keeps the intermediate
    state in LDS, plus one single step when n is odd; while a tape is recording
-   (lbm_tape_begin) every step is single.  The first paired call allocates a
+   (lbm_tape_begin) pairs are used only with an even checkpoint interval, never
+   across a checkpoint.  The first paired call allocates a
    scratch state (lbm_state_bytes, plus the x_1-face data of a second step in
    split mode) through the allocator (LBM_ENOMEM if that fails).  Asynchronous
    on the stream. */

@@ -475,9 +475,11 @@ int lbm_step(lbm_handle* h, int64_t n) {
   if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
   if (h->batch_member) return fail(h, LBM_EINVAL, "batch instances are stepped by lbm_batch_step");
   if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state (call lbm_set_initial)");
-  // pairs of steps in one bulk pass where the lattice allows it (not while a
-  // tape records checkpoints, which fall on single steps)
-  const bool pairs = h->steps_per_pass == 2 && !h->tape_active;
+  // pairs of steps in one bulk pass where the lattice allows it; while a tape
+  // records checkpoints every `every` steps, pairs only when every is even and
+  // the pair starts on an even offset, so that no checkpoint falls inside one
+  const bool pairs =
+      h->steps_per_pass == 2 && (!h->tape_active || h->tape_every % 2 == 0);
   if (pairs && n >= 2 && !h->fuse_buf) {
     h->fuse_buf = dev_alloc(h, state_bytes(h));
     if (!h->fuse_buf) return fail(h, LBM_ENOMEM, "scratch state for two-step passes");
@@ -489,7 +491,8 @@ int lbm_step(lbm_handle* h, int64_t n) {
   int64_t i = 0;
   while (i < n) {
     const int src = h->cur, dst = 1 - h->cur;
-    const int64_t todo = (pairs && n - i >= 2) ? 2 : 1;
+    const bool aligned = !h->tape_active || (h->step - h->tape_start) % 2 == 0;
+    const int64_t todo = (pairs && aligned && n - i >= 2) ? 2 : 1;
     hipEvent_t* ev = nullptr;
     if (h->profiling && h->prof_used < h->prof_cap) {
       ev = &h->prof_ev[3 * h->prof_used];

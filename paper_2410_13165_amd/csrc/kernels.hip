@@ -563,7 +563,14 @@ __global__ void __launch_bounds__(256)
 // k_step, so the result is bitwise that of two single steps.
 // Tiles fill most of the 160 KB of LDS with one block per CU: SLOTS planes of
 // (TX + 2) (TY + 2) values; a row of a tile is 256 B of one population plane.
-constexpr int kFuseZChunk = 64;
+// x_3 planes per block: 64, halved (down to 16) while the grid has fewer
+// than four blocks per CU, so that small lattices still fill the chip; every
+// chunk recomputes two step-1 planes of its neighbours.
+__host__ __device__ constexpr int fuse_zchunk(int tiles_xy, int n2) {
+  int zc = 64;
+  while (zc > 16 && tiles_xy * ((n2 + zc - 1) / zc) < 4 * 256) zc /= 2;
+  return zc;
+}
 template <class T, bool HALF>
 struct FuseShape;
 template <>
@@ -627,7 +634,8 @@ __device__ __forceinline__ void fuse_tile(const KParams& p, int TX, int TY, int&
 
 template <class T, bool HALF>
 __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
-    k_fused2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p) {
+    k_fused2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p,
+             const int zc) {
   using S = FuseShape<T, HALF>;
   constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
   constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
@@ -637,8 +645,8 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
   int tx_, ty_, tz_;
   fuse_tile(p, TX, TY, tx_, ty_, tz_);
-  const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * kFuseZChunk;
-  const int zend = min(zc0 + kFuseZChunk, n2);
+  const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * zc;
+  const int zend = min(zc0 + zc, n2);
   const int iters = zend - zc0 + 2;
   for (int it = 0; it < iters; ++it) {
     const int zp = zc0 - 1 + it;  // step-1 plane of this iteration
@@ -862,7 +870,8 @@ template <bool HALF>
 __global__ void __launch_bounds__(1024)
     k_fused2_split(const float* __restrict__ gA, float* __restrict__ gB, float* __restrict__ gC,
                    const double* __restrict__ phiA, double* __restrict__ phiB,
-                   double* __restrict__ phiC, const KParams p, const double* __restrict__ xd2) {
+                   double* __restrict__ phiC, const KParams p, const double* __restrict__ xd2,
+                   const int zc) {
   using S = FuseSplitShape<HALF>;
   constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
   constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
@@ -874,8 +883,8 @@ __global__ void __launch_bounds__(1024)
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
   int tx_, ty_, tz_;
   fuse_tile(p, TX, TY, tx_, ty_, tz_);
-  const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * kFuseZChunk;
-  const int zend = min(zc0 + kFuseZChunk, n2);
+  const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * zc;
+  const int zend = min(zc0 + zc, n2);
   const int iters = zend - zc0 + 2;
   const double oms = 1.0 - p.s;
   const double dtR = p.dt * p.R;
@@ -1402,11 +1411,11 @@ static hipError_t fused_pair_t(const KParams& p, const T* A, T* B, T* C, long lo
   }
   if (p.wall_rows > 0)
     hipLaunchKernelGGL((k_wall<3, T, TAN>), wgrid, block, 0, stream, A, C, p, t0);
-  const dim3 grid(static_cast<unsigned>(((p.n[0] + S::TX - 1) / S::TX) *
-                                        ((p.n[1] + S::TY - 1) / S::TY) *
-                                        ((p.n[2] + kFuseZChunk - 1) / kFuseZChunk)));
+  const int tiles_xy = ((p.n[0] + S::TX - 1) / S::TX) * ((p.n[1] + S::TY - 1) / S::TY);
+  const int zc = fuse_zchunk(tiles_xy, p.n[2]);
+  const dim3 grid(static_cast<unsigned>(tiles_xy * ((p.n[2] + zc - 1) / zc)));
   mark(0);
-  hipLaunchKernelGGL((k_fused2<T, HALF>), grid, dim3(S::NT), lds, stream, A, B, C, p);
+  hipLaunchKernelGGL((k_fused2<T, HALF>), grid, dim3(S::NT), lds, stream, A, B, C, p, zc);
   mark(1);
   if (p.wall_rows > 0)
     hipLaunchKernelGGL((k_wall<3, T, TAN>), wgrid, block, 0, stream, C, B, p, t1);
@@ -1454,12 +1463,12 @@ static hipError_t fused_pair_split(const KParams& p, const FusedBufs& fb, long l
   if (p.wall_rows > 0)
     hipLaunchKernelGGL((k_wall_split<3, TAN>), wgrid, block, 0, stream, gA, gC, fb.phiA, fb.phiC,
                        p, t0);
-  const dim3 grid(static_cast<unsigned>(((p.n[0] + S::TX - 1) / S::TX) *
-                                        ((p.n[1] + S::TY - 1) / S::TY) *
-                                        ((p.n[2] + kFuseZChunk - 1) / kFuseZChunk)));
+  const int tiles_xy = ((p.n[0] + S::TX - 1) / S::TX) * ((p.n[1] + S::TY - 1) / S::TY);
+  const int zc = fuse_zchunk(tiles_xy, p.n[2]);
+  const dim3 grid(static_cast<unsigned>(tiles_xy * ((p.n[2] + zc - 1) / zc)));
   mark(0);
   hipLaunchKernelGGL((k_fused2_split<HALF>), grid, dim3(S::NT), lds, stream, gA, gB, gC, fb.phiA,
-                     fb.phiB, fb.phiC, p, static_cast<const double*>(fb.xdata2));
+                     fb.phiB, fb.phiC, p, static_cast<const double*>(fb.xdata2), zc);
   mark(1);
   if (p.wall_rows > 0)
     hipLaunchKernelGGL((k_wall_split<3, TAN>), wgrid, block, 0, stream, gC, gB, fb.phiC, fb.phiB,
