@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include "engine.hpp"
+#include "fuse.hpp"
 
 namespace lbm {
 
@@ -120,6 +121,35 @@ __device__ __forceinline__ void block_sum(double v, double* sh, double* out,
   if (tid == 0) *out = accumulate ? *out + sh[0] : sh[0];
 }
 
+// acc + <mu, (omega 1^T - I) f^n> at one node, f^n recovered from the stored
+// forward state g (post-collision, or the split g_k = f_k - omega_k phi).
+template <int D, class T>
+__device__ __forceinline__ double zdot(double acc, const T (&mu)[q_of(D)], const T* __restrict__ g,
+                                       int node, long long ps, int mode, const KParams& p) {
+  constexpr int Q = q_of(D);
+  double z[Q];
+  if (mode == kSplit) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) z[k] = -static_cast<double>(g[k * ps + node]);
+  } else {
+    // omega_k phi + dt omega_k R - g_k with phi = sum_j g_j - dt R, which is
+    // omega_k sum_j g_j - g_k; the same form holds for the float32
+    // deviations from the uniform state
+    double gk[Q];
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      gk[k] = static_cast<double>(g[k * ps + node]);
+      sum += gk[k];
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) z[k] = p.omega[k] * sum - gk[k];
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) acc += static_cast<double>(mu[k]) * z[k];
+  return acc;
+}
+
 }  // namespace
 
 // One adjoint step lambda^{n+1} -> lambda^n over every row.  `g` is the
@@ -166,32 +196,137 @@ __global__ void __launch_bounds__(256)
       const T oms = static_cast<T>(1.0 - p.s);
 #pragma unroll
       for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(oms * mu[k] + ms, ldst + k * ps + node);
-      if (g) {
-        // (omega 1^T - I) f^n at this node
-        double z[Q];
-        if (mode == kSplit) {
-#pragma unroll
-          for (int k = 0; k < Q; ++k) z[k] = -static_cast<double>(g[k * ps + node]);
-        } else {
-          // omega_k phi + dt omega_k R - g_k with phi = sum_j g_j - dt R, which is
-          // omega_k sum_j g_j - g_k; the same form holds for the float32
-          // deviations from the uniform state
-          double gk[Q];
-          double sum = 0.0;
-#pragma unroll
-          for (int k = 0; k < Q; ++k) {
-            gk[k] = static_cast<double>(g[k * ps + node]);
-            sum += gk[k];
-          }
-#pragma unroll
-          for (int k = 0; k < Q; ++k) z[k] = p.omega[k] * sum - gk[k];
-        }
-#pragma unroll
-        for (int k = 0; k < Q; ++k) acc += static_cast<double>(mu[k]) * z[k];
-      }
+      if (g) acc = zdot<D, T>(acc, mu, g, node, ps, mode, p);
     }
   }
   if (g) block_sum(acc, sh, partial + blockIdx.x, true);
+}
+
+// Two adjoint steps lambda^{n+1} -> lambda^{n-1} in one pass (d = 3), laid
+// out as the forward two-step pass (fuse.hpp) but pulling from x + c_k, so
+// the LDS planes of the c_3 = -1 values are the long-lived ones.  g1 and g2
+// are the forward states at steps n and n - 1 (both null when no dL/ds is
+// wanted); each block adds its share of both steps' contractions to
+// partial[block] (its own nodes only: the halo belongs to other blocks).
+template <class T, bool HALF>
+__global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
+    k_adjoint2(const T* __restrict__ lsrc, T* __restrict__ ldst, const T* __restrict__ g1,
+               const T* __restrict__ g2, const KParams p, const int mode,
+               double* __restrict__ partial, const int zc) {
+  using S = FuseShape<T, HALF>;
+  constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
+  constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  T* lds = reinterpret_cast<T*>(fuse_lds);
+  const long long ps = p.pstride;
+  const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+  int tx_, ty_, tz_;
+  fuse_tile(p, TX, TY, tx_, ty_, tz_);
+  const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * zc;
+  const int zend = min(zc0 + zc, n2);
+  const int iters = zend - zc0 + 2;
+  const T oms = static_cast<T>(1.0 - p.s);
+  double acc = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    const int zp = zc0 - 1 + it;
+    // ---- lambda^n on the tile and its halo of plane zp
+    for (int r = threadIdx.x; r < R; r += NT) {
+      const int rx = r % RX, ry = r / RX;
+      int gx = x0 - 1 + rx, gy = y0 - 1 + ry, gz = zp;
+      if (gx < 0 || gx >= n0) {
+        if (p.bc[0] != 0) continue;
+        gx = fuse_wrap(gx, n0);
+      }
+      if (gy < 0 || gy >= n1) {
+        if (p.bc[1] != 0) continue;
+        gy = fuse_wrap(gy, n1);
+      }
+      if (gz < 0 || gz >= n2) {
+        if (p.bc[2] != 0) continue;
+        gz = fuse_wrap(gz, n2);
+      }
+      Nb<D> nb;
+      nb_row<D>(p, gz * n1 + gy, nb);
+      nb_col<D>(p, gx, nb);
+      const int node = nb.rowbase + gx;
+      T mu[Q];
+      sfor<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        mu[k] = lsrc[k * ps + node + push_offset<D, k>(nb)];
+      });
+      sfor<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if (leaves<D, k>(nb)) {
+          constexpr int kb = opp_index(D, k);
+          mu[k] = HALF ? -lsrc[kb * ps + node] : T(0);
+        }
+      });
+      double m = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) m += p.omega[k] * static_cast<double>(mu[k]);
+      const T ms = static_cast<T>(p.s * m);
+      const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
+                       y0 - 1 + ry < n1 && zp >= zc0 && zp < zend;
+      if (g1 && own) acc = zdot<D, T>(acc, mu, g1, node, ps, mode, p);
+      sfor<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        lds[adj_slot<HALF, k>(it) * R + r] = oms * mu[k] + ms;
+      });
+    }
+    __syncthreads();
+    // ---- lambda^{n-1} on output plane zp - 1
+    if (it >= 2) {
+      const int gz = zp - 1;
+      for (int o = threadIdx.x; o < TX * TY; o += NT) {
+        const int ox = o % TX, oy = o / TX;
+        const int gx = x0 + ox, gy = y0 + oy;
+        if (gx >= n0 || gy >= n1) continue;
+        Nb<D> nb;
+        nb_row<D>(p, gz * n1 + gy, nb);
+        nb_col<D>(p, gx, nb);
+        const int node = nb.rowbase + gx;
+        const int own = (oy + 1) * RX + (ox + 1);
+        T mu[Q];
+        sfor<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr CV4 c = cvec(D, k);
+          constexpr int src_it = c.v[2] == 1 ? 0 : (c.v[2] == 0 ? 1 : 2);
+          if (leaves<D, k>(nb)) {
+            if constexpr (HALF) {
+              constexpr int kb = opp_index(D, k);
+              mu[k] = -lds[adj_slot<HALF, kb>(it - 1) * R + own];
+            } else {
+              mu[k] = T(0);
+            }
+          } else {
+            const int rr = (oy + 1 + c.v[1]) * RX + (ox + 1 + c.v[0]);
+            mu[k] = lds[adj_slot<HALF, k>(it - src_it) * R + rr];
+          }
+        });
+        double m = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) m += p.omega[k] * static_cast<double>(mu[k]);
+        const T ms = static_cast<T>(p.s * m);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          __builtin_nontemporal_store(oms * mu[k] + ms, ldst + k * ps + node);
+        if (g2) acc = zdot<D, T>(acc, mu, g2, node, ps, mode, p);
+      }
+    }
+    __syncthreads();
+  }
+  if (g1 || g2) {
+    // deterministic block sum over 1024 slots (zeros past NT), reusing the LDS
+    double* sh = reinterpret_cast<double*>(fuse_lds);
+    sh[threadIdx.x] = acc;
+    if (threadIdx.x + NT < 1024) sh[threadIdx.x + NT] = 0.0;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+      if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] += sh[0];
+  }
 }
 
 // Seed lambda^N_k(x) = dL/dphi^N(x) for every k.
@@ -320,6 +455,59 @@ static hipError_t adjoint_d(const KParams& p, int mode, const void* lsrc, void* 
                        static_cast<const float*>(lsrc), static_cast<float*>(ldst),
                        static_cast<const float*>(g), gphi, p, mode, partial);
   return hipGetLastError();
+}
+
+template <class T>
+static long long pair_blocks_t(const KParams& p) {
+  using S = FuseShape<T, false>;
+  using H = FuseShape<T, true>;
+  const bool half = p.scheme == kHalfWay;
+  const int tx = half ? H::TX : S::TX, ty = half ? H::TY : S::TY;
+  const int tiles_xy = ((p.n[0] + tx - 1) / tx) * ((p.n[1] + ty - 1) / ty);
+  const int zc = fuse_zchunk(tiles_xy, p.n[2]);
+  return static_cast<long long>(tiles_xy) * ((p.n[2] + zc - 1) / zc);
+}
+
+long long adjoint_pair_blocks(const KParams& p, int mode) {
+  if (p.d != 3) return 0;
+  return mode == kFP64 ? pair_blocks_t<double>(p) : pair_blocks_t<float>(p);
+}
+
+template <class T, bool HALF>
+static hipError_t adjoint_pair_t(const KParams& p, int mode, const void* lsrc, void* ldst,
+                                 const void* g1, const void* g2, double* partial,
+                                 hipStream_t stream) {
+  using S = FuseShape<T, HALF>;
+  constexpr int R = (S::TX + 2) * (S::TY + 2);
+  constexpr size_t lds = sizeof(T) * S::SLOTS * R;
+  static_assert(lds <= 160 * 1024 && lds >= 1024 * sizeof(double), "LDS of the adjoint pass");
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint2<T, HALF>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int tiles_xy = ((p.n[0] + S::TX - 1) / S::TX) * ((p.n[1] + S::TY - 1) / S::TY);
+  const int zc = fuse_zchunk(tiles_xy, p.n[2]);
+  const dim3 grid(static_cast<unsigned>(tiles_xy * ((p.n[2] + zc - 1) / zc)));
+  hipLaunchKernelGGL((k_adjoint2<T, HALF>), grid, dim3(S::NT), lds, stream,
+                     static_cast<const T*>(lsrc), static_cast<T*>(ldst),
+                     static_cast<const T*>(g1), static_cast<const T*>(g2), p, mode, partial, zc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_pair(const KParams& p, int mode, const void* lsrc, void* ldst,
+                               const void* g1, const void* g2, double* partial,
+                               hipStream_t stream) {
+  if (p.d != 3) return hipErrorInvalidValue;
+  const bool half = p.scheme == kHalfWay;
+  if (mode == kFP64)
+    return half ? adjoint_pair_t<double, true>(p, mode, lsrc, ldst, g1, g2, partial, stream)
+                : adjoint_pair_t<double, false>(p, mode, lsrc, ldst, g1, g2, partial, stream);
+  return half ? adjoint_pair_t<float, true>(p, mode, lsrc, ldst, g1, g2, partial, stream)
+              : adjoint_pair_t<float, false>(p, mode, lsrc, ldst, g1, g2, partial, stream);
 }
 
 hipError_t launch_adjoint_step(const KParams& p, int mode, const void* lsrc, void* ldst,

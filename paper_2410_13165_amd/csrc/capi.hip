@@ -709,7 +709,12 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
     owned.clear();
   };
   void* lam[2] = {alloc(pb), alloc(pb)};
-  double* partial = static_cast<double*>(alloc(sizeof(double) * (shp.blocks + 65536)));
+  // adjoint passes of two steps (d = 3) pair the adjoint steps within each
+  // segment
+  const bool pairs = h->steps_per_pass == 2;
+  const long long npart =
+      std::max<long long>(shp.blocks, pairs ? adjoint_pair_blocks(kp, h->precision) : 0);
+  double* partial = static_cast<double*>(alloc(sizeof(double) * npart));
   // dsteps[0]: sum over the steps of the dL/ds contractions; dsteps[1]: the
   // initialisation's tau term
   double* dsteps = static_cast<double*>(alloc(sizeof(double) * 2));
@@ -725,7 +730,7 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
   }
   hipError_t e = hipMemsetAsync(lam[0], 0, pb, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(lam[1], 0, pb, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(partial, 0, sizeof(double) * shp.blocks, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(partial, 0, sizeof(double) * npart, h->stream);
   if (e == hipSuccess) e = launch_adjoint_seed(kp, h->precision, dl_dphi_dev, lam[0], h->stream);
   int cur = 0;
   for (int64_t sgi = nseg - 1; sgi >= 0 && e == hipSuccess; --sgi) {
@@ -735,6 +740,9 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
     std::vector<void*> st;
     if (want_tau) {
       st.push_back(h->tape_ckpt[sgi]);
+      // single steps: every state is stored, and a two-step pass that also
+      // stores its intermediate state moves more bytes per second of its
+      // slower, LDS-bound schedule than it saves (measured)
       for (int64_t n = s0 + 1; n < s1 && e == hipSuccess; ++n) {
         void* src = st.back();
         void* dst = seg[n - s0 - 1];
@@ -743,16 +751,24 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
         st.push_back(dst);
       }
     }
-    for (int64_t n = s1 - 1; n >= s0 && e == hipSuccess; --n) {
+    for (int64_t n = s1 - 1; n >= s0 && e == hipSuccess;) {
       const void* g = want_tau ? st[n - s0] : nullptr;
-      e = launch_adjoint_step(kp, h->precision, lam[cur], lam[1 - cur], g,
-                              want_tau ? blob_phi(h, const_cast<void*>(g)) : nullptr, partial,
-                              h->stream);
+      if (pairs && n - 1 >= s0) {
+        const void* g2 = want_tau ? st[n - 1 - s0] : nullptr;
+        e = launch_adjoint_pair(kp, h->precision, lam[cur], lam[1 - cur], g, g2, partial,
+                                h->stream);
+        n -= 2;
+      } else {
+        e = launch_adjoint_step(kp, h->precision, lam[cur], lam[1 - cur], g,
+                                want_tau ? blob_phi(h, const_cast<void*>(g)) : nullptr, partial,
+                                h->stream);
+        n -= 1;
+      }
       cur = 1 - cur;
     }
   }
   // dL/ds (without the 1/(1-s) of the post-collision modes), summed over the steps
-  if (e == hipSuccess && want_tau) e = launch_sum_partials(partial, shp.blocks, dsteps, h->stream);
+  if (e == hipSuccess && want_tau) e = launch_sum_partials(partial, npart, dsteps, h->stream);
   if (e != hipSuccess) {
     cleanup();
     return hip_fail(h, e, "adjoint kernels");

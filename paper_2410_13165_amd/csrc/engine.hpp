@@ -143,6 +143,14 @@ hipError_t launch_batch(int d, const KParams* kps, void* const* bufs, const Batc
 hipError_t launch_adjoint_step(const KParams& p, int mode, const void* lsrc, void* ldst,
                                const void* g, const double* gphi, double* partial,
                                hipStream_t stream);
+// Two adjoint steps lambda^{n+1} -> lambda^{n-1} in one pass (d = 3; the
+// layout of the forward two-step pass).  g1, g2: forward states at steps n and
+// n - 1 (both nullable); their contractions are added to
+// partial[0 .. adjoint_pair_blocks(p, mode)).
+hipError_t launch_adjoint_pair(const KParams& p, int mode, const void* lsrc, void* ldst,
+                               const void* g1, const void* g2, double* partial,
+                               hipStream_t stream);
+long long adjoint_pair_blocks(const KParams& p, int mode);
 hipError_t launch_adjoint_seed(const KParams& p, int mode, const double* dldphi, void* lam,
                                hipStream_t stream);
 // Transpose of the initialisation; partial[0 .. *nblocks) receives the

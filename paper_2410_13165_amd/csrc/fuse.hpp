@@ -1,0 +1,99 @@
+// Shared pieces of the two-step (fused) passes: tile shapes, the LDS plane
+// slots of the step-1 values, and the tile order (kernels.hip forward passes,
+// adjoint.hip adjoint passes).  D = 3 only; the passes march along x_3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "engine.hpp"
+
+namespace lbm {
+
+// x_3 planes per block: 64, halved (down to 16) while the grid has fewer
+// than four blocks per CU, so that small lattices still fill the chip; every
+// chunk recomputes two step-1 planes of its neighbours.
+__host__ __device__ constexpr int fuse_zchunk(int tiles_xy, int n2) {
+  int zc = 64;
+  while (zc > 16 && tiles_xy * ((n2 + zc - 1) / zc) < 4 * 256) zc /= 2;
+  return zc;
+}
+
+// Tiles fill most of the 160 KB of LDS with one block per CU: SLOTS planes of
+// (TX + 2) (TY + 2) values; a row of a tile is 256 B of one population plane.
+template <class T, bool HALF>
+struct FuseShape;
+template <>
+struct FuseShape<float, false> {
+  static constexpr int TX = 64, TY = 13, NT = 1024, SLOTS = 38;
+};
+template <>
+struct FuseShape<float, true> {
+  static constexpr int TX = 64, TY = 11, NT = 896, SLOTS = 43;
+};
+template <>
+struct FuseShape<double, false> {
+  static constexpr int TX = 32, TY = 12, NT = 512, SLOTS = 38;
+};
+template <>
+struct FuseShape<double, true> {
+  static constexpr int TX = 32, TY = 12, NT = 512, SLOTS = 43;
+};
+
+// index of population k among those with the same c_3
+constexpr int cz_index(int k) {
+  const int cz = vel_comp(3, k, 2);
+  int idx = 0;
+  for (int m = 0; m < k; ++m)
+    if (vel_comp(3, m, 2) == cz) ++idx;
+  return idx;
+}
+
+// LDS plane slot of population k for the step-1 plane produced at iteration it
+// of a forward pass: step 2 on plane z reads k from plane z - c_3, so c_3 = +1
+// values live three iterations, c_3 = 0 two and c_3 = -1 one (two with
+// half-way walls, which also read the node's own opposite population).
+template <bool HALF, int k>
+__device__ __forceinline__ int fuse_slot(int it) {
+  constexpr int cz = vel_comp(3, k, 2);
+  constexpr int i = cz_index(k);
+  if constexpr (cz == 0) return 2 * i + (it & 1);
+  else if constexpr (cz == 1) return 18 + 3 * i + it % 3;
+  else if constexpr (HALF) return 33 + 2 * i + (it & 1);
+  else return 33 + i;
+}
+
+__device__ __forceinline__ int fuse_wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Tile of this block.  Workgroups go to the 8 XCDs round-robin by index, so
+// block b is given tile (b mod 8) * per + b / 8: each XCD walks a contiguous
+// run of tiles in x_1-fastest order, and the tiles next to each other in x_1
+// and x_2, whose halos read the same cache lines, run at the same time under
+// one L2.
+__device__ __forceinline__ void fuse_tile(const KParams& p, int TX, int TY, int& bx, int& by,
+                                          int& bz) {
+  const int gx = (p.n[0] + TX - 1) / TX, gy = (p.n[1] + TY - 1) / TY;
+  const int nb = static_cast<int>(gridDim.x);
+  const int per = nb / 8;
+  const int b = static_cast<int>(blockIdx.x);
+  const int t = (b < 8 * per) ? (b % 8) * per + b / 8 : b;
+  bx = t % gx;
+  by = (t / gx) % gy;
+  bz = t / (gx * gy);
+}
+
+// The same for an adjoint pass, which reads k from plane z + c_3: the roles
+// of c_3 = +1 and c_3 = -1 swap.
+template <bool HALF, int k>
+__device__ __forceinline__ int adj_slot(int it) {
+  constexpr int cz = vel_comp(3, k, 2);
+  constexpr int i = cz_index(k);
+  if constexpr (cz == 0) return 2 * i + (it & 1);
+  else if constexpr (cz == -1) return 18 + 3 * i + it % 3;
+  else if constexpr (HALF) return 33 + 2 * i + (it & 1);
+  else return 33 + i;
+}
+
+}  // namespace lbm

@@ -90,6 +90,7 @@ CASES = [
     (2, (7, 6), ["halfway"] * 2, 3, True),
     (3, (5, 4, 4), ["periodic"] * 3, 3, False),
     (3, (5, 5, 4), ["fullway"] * 3, 3, True),
+    (3, (4, 5, 4), ["halfway"] * 3, 3, True),
 ]
 
 
@@ -204,3 +205,33 @@ def test_autograd_function_matches_finite_differences():
     h = 1e-5
     fdt = (L(phi0.detach(), 0.6 + h) - L(phi0.detach(), 0.6 - h)) / (2 * h)
     assert abs(float(tau.grad) - fdt) <= 1e-6 * max(1.0, abs(fdt))
+
+
+@pytest.mark.parametrize("prec,bc,tol", [("fp64", "fullway", 1e-12), ("fp64", "halfway", 1e-12),
+                                         ("fp32", "periodic", 2e-6),
+                                         ("fp32_split", "fullway", 2e-6)])
+def test_two_step_adjoint_matches_single_steps(prec, bc, tol):
+    """d = 3: the replay and the adjoint advanced two steps per pass give the
+    gradients of the single-step passes (to rounding of the reduction order)."""
+    from paper_2410_13165_amd import Lattice
+    d, dims = 3, (40, 30, 37)
+    spec = inputs.random_cosines(3, [0.05, -0.1, 0.08], 0.4, seed=77, kmax=1.0)
+    rng = np.random.default_rng(78)
+    target = torch.from_numpy(rng.normal(size=tuple(reversed(dims))))
+    out = []
+    for spp in (2, 1):
+        lat = Lattice(d, dims, 0.55, dx=1.0 / 39, u=spec["u"], R=spec.get("R", 0.0),
+                      bc=[bc] * 3, precision=prec, field=spec, steps_per_pass=spp)
+        try:
+            lat.tape_begin(6)
+            lat.step(23)
+            res = lat.phi() - target.to(lat.phi().device)
+            g = lat.tape_gradient(res, want_phi0=True, want_tau=True)
+            out.append((g["phi0"].cpu().numpy(), g["tau"]))
+            lat.tape_end()
+        finally:
+            lat.close()
+    (a, ta), (b, tb) = out
+    assert np.max(np.abs(a - b)) <= tol * np.max(np.abs(b))
+    assert abs(ta - tb) <= tol * max(1.0, abs(tb)), (ta, tb)
+
