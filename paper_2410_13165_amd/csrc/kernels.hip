@@ -86,6 +86,26 @@ __device__ __forceinline__ void row_setup(const KParams& p, int row, RowInfo<D>&
   r.rowbase = row * p.n[0];
 }
 
+// row_setup for d = 3 from the row's coordinates (i_2, i_3), without the
+// divisions that recover them from the row index
+__device__ __forceinline__ void row_setup_yz(const KParams& p, int iy, int iz, RowInfo<3>& r) {
+  const int ia[3] = {0, iy, iz};
+  r.rowwall = false;
+#pragma unroll
+  for (int a = 1; a < 3; ++a) {
+    const int n = p.n[a];
+    const int st = p.stride[a];
+    r.i[a] = ia[a];
+    r.dm[a] = (ia[a] == 0) ? (n - 1) * st : -st;
+    r.dp[a] = (ia[a] == n - 1) ? -(n - 1) * st : st;
+    const bool wall = p.bc[a] != 0;
+    r.lo[a] = wall && ia[a] == 0;
+    r.hi[a] = wall && ia[a] == n - 1;
+    r.rowwall = r.rowwall || r.lo[a] || r.hi[a];
+  }
+  r.rowbase = (iz * p.n[1] + iy) * p.n[0];
+}
+
 template <int D>
 __device__ __forceinline__ void col_setup(const KParams& p, int x, RowInfo<D>& r) {
   const int n0 = p.n[0];
@@ -598,7 +618,7 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
       }
       const int row = gz * n1 + gy;
       RowInfo<D> ri;
-      row_setup<D>(p, row, ri);
+      row_setup_yz(p, gy, gz, ri);
       col_setup<D>(p, gx, ri);
       const int node = ri.rowbase + gx;
       T f[Q];
@@ -653,7 +673,7 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
         if (gx >= n0 || gy >= n1) continue;
         const int row = gz * n1 + gy;
         RowInfo<D> ri;
-        row_setup<D>(p, row, ri);
+        row_setup_yz(p, gy, gz, ri);
         if (ri.rowwall) continue;
         col_setup<D>(p, gx, ri);
         const int node = ri.rowbase + gx;
@@ -837,7 +857,7 @@ __global__ void __launch_bounds__(1024)
       }
       const int row = gz * n1 + gy;
       RowInfo<D> ri;
-      row_setup<D>(p, row, ri);
+      row_setup_yz(p, gy, gz, ri);
       col_setup<D>(p, gx, ri);
       const int node = ri.rowbase + gx;
       float g[Q];
@@ -896,7 +916,7 @@ __global__ void __launch_bounds__(1024)
         if (gx >= n0 || gy >= n1) continue;
         const int row = gz * n1 + gy;
         RowInfo<D> ri;
-        row_setup<D>(p, row, ri);
+        row_setup_yz(p, gy, gz, ri);
         if (ri.rowwall) continue;
         col_setup<D>(p, gx, ri);
         const int node = ri.rowbase + gx;
