@@ -809,15 +809,15 @@ template <bool HALF>
 struct FuseSplitShape;
 template <>
 struct FuseSplitShape<false> {
-  static constexpr int TX = 64, TY = 11, NT = 1024, SLOTS = 38;
+  static constexpr int TX = 64, TY = 11, NT = 512, SLOTS = 38;
 };
 template <>
 struct FuseSplitShape<true> {
-  static constexpr int TX = 64, TY = 10, NT = 1024, SLOTS = 43;
+  static constexpr int TX = 64, TY = 10, NT = 512, SLOTS = 43;
 };
 
 template <bool HALF>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
     k_fused2_split(const float* __restrict__ gA, float* __restrict__ gB, float* __restrict__ gC,
                    const double* __restrict__ phiA, double* __restrict__ phiB,
                    double* __restrict__ phiC, const KParams p, const double* __restrict__ xd2,
