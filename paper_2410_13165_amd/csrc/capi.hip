@@ -610,12 +610,12 @@ void destroy_events(lbm_handle* h) {
 }
 }  // namespace
 
-int lbm_profile_begin(lbm_handle* h, int64_t max_steps) {
+int lbm_profile_begin(lbm_handle* h, int64_t max_launches) {
   if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
   if (h->profiling) return fail(h, LBM_EINVAL, "profiling already active");
-  if (max_steps < 1 || max_steps > (int64_t(1) << 20))
-    return fail(h, LBM_EINVAL, "max_steps must be in 1..2^20");
-  h->prof_ev.assign(static_cast<size_t>(3 * max_steps), nullptr);
+  if (max_launches < 1 || max_launches > (int64_t(1) << 20))
+    return fail(h, LBM_EINVAL, "max_launches must be in 1..2^20");
+  h->prof_ev.assign(static_cast<size_t>(3 * max_launches), nullptr);
   for (auto& e : h->prof_ev) {
     hipError_t rc = hipEventCreate(&e);
     if (rc != hipSuccess) {
@@ -623,7 +623,7 @@ int lbm_profile_begin(lbm_handle* h, int64_t max_steps) {
       return hip_fail(h, rc, "hipEventCreate");
     }
   }
-  h->prof_cap = max_steps;
+  h->prof_cap = max_launches;
   h->prof_used = 0;
   h->prof_steps = 0;
   h->profiling = true;

@@ -381,8 +381,8 @@ class Lattice:
             out["tau"] = tau.value
         return out
 
-    def profile_begin(self, max_steps: int):
-        self._check(self.lib.lbm_profile_begin(self._h, int(max_steps)))
+    def profile_begin(self, max_launches: int):
+        self._check(self.lib.lbm_profile_begin(self._h, int(max_launches)))
         return self
 
     def profile_end(self) -> dict:
