@@ -135,10 +135,10 @@ typedef struct {
   void* stream;                 /* hipStream_t used for all work, borrowed            */
   int32_t wall_data;            /* lbm_wall_data; default LBM_WALL_JETS               */
   int32_t steps_per_pass;       /* 2 (default): lattices with d = 3 (every storage
-                                   mode) advance two time steps per pass of the bulk
-                                   kernel (bitwise the same result, about half the
-                                   HBM traffic); 1: one step per pass.  Lattices with
-                                   d != 3 always use 1.                                */
+                                   mode) or d = 2 (LBM_FP32, LBM_FP64) advance two
+                                   time steps per pass of the bulk kernel (bitwise the
+                                   same result, about half the HBM traffic); 1: one
+                                   step per pass.  Other lattices always use 1.        */
 } lbm_params;
 
 typedef struct {
@@ -184,7 +184,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p,
 int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_phi0_dev);
 
 /* Advance n >= 0 time steps of the fused pull-stream + collide kernel with
-   the wall schemes applied inline.  With steps_per_pass = 2 (d = 3)
+   the wall schemes applied inline.  With steps_per_pass = 2 (see lbm_params)
    the steps go in pairs through one bulk pass that keeps the intermediate
    state in LDS, plus one single step when n is odd; while a tape is recording
    (lbm_tape_begin) pairs are used only with an even checkpoint interval, never

@@ -318,7 +318,9 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   h->q = q_of(d);
   h->nodes = nodes;
   h->precision = p->precision;
-  h->steps_per_pass = (p->steps_per_pass == 2 && d == 3) ? 2 : 1;
+  h->steps_per_pass =
+      (p->steps_per_pass == 2 && (d == 3 || (d == 2 && p->precision != LBM_FP32_SPLIT))) ? 2
+                                                                                        : 1;
   h->stream = static_cast<hipStream_t>(p->stream);
   h->alloc = p->alloc;
   h->free_fn = p->free_fn;
@@ -711,7 +713,7 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
   void* lam[2] = {alloc(pb), alloc(pb)};
   // adjoint passes of two steps (d = 3) pair the adjoint steps within each
   // segment
-  const bool pairs = h->steps_per_pass == 2;
+  const bool pairs = h->steps_per_pass == 2 && h->d == 3;
   const long long npart =
       std::max<long long>(shp.blocks, pairs ? adjoint_pair_blocks(kp, h->precision) : 0);
   double* partial = static_cast<double*>(alloc(sizeof(double) * npart));

@@ -96,4 +96,48 @@ __device__ __forceinline__ int adj_slot(int it) {
   else return 33 + i;
 }
 
+// ---- d = 2: 1-D tiles along x_1 marching along x_2 (the same plan with
+// planes replaced by rows).  The c_2 classes of D2Q9 have three members each.
+template <class T, bool HALF>
+struct FuseShape2 {
+  static constexpr int TX = 254, NT = 256, SLOTS = HALF ? 21 : 18;
+};
+
+constexpr int cy_index(int k) {
+  const int cy = vel_comp(2, k, 1);
+  int idx = 0;
+  for (int m = 0; m < k; ++m)
+    if (vel_comp(2, m, 1) == cy) ++idx;
+  return idx;
+}
+
+template <bool HALF, int k>
+__device__ __forceinline__ int fuse_slot2(int it) {
+  constexpr int cy = vel_comp(2, k, 1);
+  constexpr int i = cy_index(k);
+  if constexpr (cy == 0) return 2 * i + (it & 1);
+  else if constexpr (cy == 1) return 6 + 3 * i + it % 3;
+  else if constexpr (HALF) return 15 + 2 * i + (it & 1);
+  else return 15 + i;
+}
+
+// x_2 rows per block: 64, halved (down to 8) while the grid has fewer than
+// four blocks per CU
+__host__ __device__ constexpr int fuse_ychunk(int tiles_x, int n1) {
+  int yc = 64;
+  while (yc > 8 && tiles_x * ((n1 + yc - 1) / yc) < 4 * 256) yc /= 2;
+  return yc;
+}
+
+// tile of this block for d = 2, in the XCD-aware order of fuse_tile
+__device__ __forceinline__ void fuse_tile2(const KParams& p, int TX, int& bx, int& by) {
+  const int gx = (p.n[0] + TX - 1) / TX;
+  const int nb = static_cast<int>(gridDim.x);
+  const int per = nb / 8;
+  const int b = static_cast<int>(blockIdx.x);
+  const int t = (b < 8 * per) ? (b % 8) * per + b / 8 : b;
+  bx = t % gx;
+  by = t / gx;
+}
+
 }  // namespace lbm

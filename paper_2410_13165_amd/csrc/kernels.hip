@@ -710,6 +710,133 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
   }
 }
 
+// The two-step pass for d = 2: a block owns TX nodes of x_1 and a chunk of
+// x_2 rows and marches along x_2 (rows play the part of the planes of
+// k_fused2, with no halo across x_2 besides the marching itself).  Rows on a
+// Dirichlet wall of x_2 go through C as in k_fused2.
+template <class T, bool HALF>
+__global__ void __launch_bounds__(256)
+    k_fused2_d2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p,
+                const int yc) {
+  using S = FuseShape2<T, HALF>;
+  constexpr int D = 2, Q = q_of(2), TX = S::TX, NT = S::NT;
+  constexpr int R = TX + 2;
+  static_assert(R == NT, "one region node per thread");
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  T* lds = reinterpret_cast<T*>(fuse_lds);
+  const long long ps = p.pstride;
+  const int n0 = p.n[0], n1 = p.n[1];
+  int tx_, ty_;
+  fuse_tile2(p, TX, tx_, ty_);
+  const int x0 = tx_ * TX, yc0 = ty_ * yc;
+  const int yend = min(yc0 + yc, n1);
+  const int iters = yend - yc0 + 2;
+  const int r = threadIdx.x;
+  for (int it = 0; it < iters; ++it) {
+    const int yp = yc0 - 1 + it;  // step-1 row of this iteration
+    // ---- step 1 on the tile and its halo of row yp
+    {
+      int gx = x0 - 1 + r, gy = yp;
+      bool skip = false;
+      if (gx < 0 || gx >= n0) {
+        if (p.bc[0] != 0) skip = true;
+        else gx = fuse_wrap(gx, n0);
+      }
+      if (gy < 0 || gy >= n1) {
+        if (p.bc[1] != 0) skip = true;
+        else gy = fuse_wrap(gy, n1);
+      }
+      if (!skip) {
+        const int row = gy;
+        RowInfo<D> ri;
+        row_setup<D>(p, row, ri);
+        col_setup<D>(p, gx, ri);
+        const int node = ri.rowbase + gx;
+        T f[Q];
+        if (ri.rowwall) {
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            f[k] = C[k * ps + node];
+          });
+        } else {
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            int idx = node + pull_offset<D, k>(ri);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) idx = p.xoff + row;
+            }
+            f[k] = A[k * ps + idx];
+          });
+          if (HALF && (ri.lo[0] || ri.hi[0])) {
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] -= A[opp_index(D, k) * ps + node];
+              }
+            });
+          }
+          collide_vals<D, T>(f, p);
+          // rows next to a wall of x_2, owned by this block: kept for the
+          // step-2 wall kernel
+          const bool own = r >= 1 && r <= TX && x0 - 1 + r < n0 && yp >= yc0 && yp < yend;
+          const bool near = p.bc[1] != 0 && (ri.i[1] == 1 || ri.i[1] == n1 - 2);
+          if (own && near) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(f[k], C + k * ps + node);
+          }
+        }
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          lds[fuse_slot2<HALF, k>(it) * R + r] = f[k];
+        });
+      }
+    }
+    __syncthreads();
+    // ---- step 2 on output row yp - 1
+    if (it >= 2 && r < TX) {
+      const int gy = yp - 1;
+      const int gx = x0 + r;
+      if (gx < n0) {
+        const int row = gy;
+        RowInfo<D> ri;
+        row_setup<D>(p, row, ri);
+        if (!ri.rowwall) {
+          col_setup<D>(p, gx, ri);
+          const int node = ri.rowbase + gx;
+          T f[Q];
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr Vec4i c = vel_vec(D, k);
+            constexpr int src_it = c.v[1] == 0 ? 1 : (c.v[1] == 1 ? 2 : 0);
+            bool face = false;
+            if constexpr (c.v[0] != 0) face = (c.v[0] == 1) ? ri.lo[0] : ri.hi[0];
+            if (face) {
+              f[k] = B[k * ps + p.xoff + row];
+            } else {
+              f[k] = lds[fuse_slot2<HALF, k>(it - src_it) * R + (r + 1 - c.v[0])];
+            }
+          });
+          if (HALF && (ri.lo[0] || ri.hi[0])) {
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                constexpr int kb = opp_index(D, k);
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0])
+                  f[k] -= lds[fuse_slot2<HALF, kb>(it - 1) * R + (r + 1)];
+              }
+            });
+          }
+          collide_store<D, T>(f, B, ps, node, p);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Many lattices in one launch (periodic instances): block b updates rows
 // tiles[b].row0 .. + blockDim.y - 1 of instance tiles[b].inst, whose parameter
 // block is kps[inst] and whose two state buffers are bufs[2 inst], bufs[2 inst + 1]
@@ -1442,8 +1569,69 @@ static hipError_t fused_pair_m(const KParams& p, const FusedBufs& fb, long long 
               : fused_pair_t<T, false, false>(p, a, b, c, n, stream, ev);
 }
 
+template <class T, bool TAN, bool HALF>
+static hipError_t fused_pair2_t(const KParams& p, const T* A, T* B, T* C, long long n,
+                                hipStream_t stream, hipEvent_t* ev) {
+  using S = FuseShape2<T, HALF>;
+  constexpr size_t lds = sizeof(T) * S::SLOTS * (S::TX + 2);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused2_d2<T, HALF>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  constexpr int mode = std::is_same<T, float>::value ? kFP32 : kFP64;
+  const LaunchShape s = step_shape(p);
+  const dim3 block(s.tx, s.ty);
+  const dim3 wgrid(static_cast<unsigned>((p.wall_rows + s.ty - 1) / s.ty));
+  const double t0 = static_cast<double>(n) * p.dt, t1 = static_cast<double>(n + 1) * p.dt;
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], stream);
+  };
+  if (p.bc[0] != 0) {
+    const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
+    hipLaunchKernelGGL((k_xface<2, T, TAN>), dim3(xb), dim3(256), 0, stream, const_cast<T*>(A),
+                       p, t0, mode);
+    hipLaunchKernelGGL((k_xface<2, T, TAN>), dim3(xb), dim3(256), 0, stream, B, p, t1, mode);
+  }
+  if (p.wall_rows > 0)
+    hipLaunchKernelGGL((k_wall<2, T, TAN>), wgrid, block, 0, stream, A, C, p, t0);
+  const int tiles_x = (p.n[0] + S::TX - 1) / S::TX;
+  const int yc = fuse_ychunk(tiles_x, p.n[1]);
+  const dim3 grid(static_cast<unsigned>(tiles_x * ((p.n[1] + yc - 1) / yc)));
+  mark(0);
+  hipLaunchKernelGGL((k_fused2_d2<T, HALF>), grid, dim3(S::NT), lds, stream, A, B, C, p, yc);
+  mark(1);
+  if (p.wall_rows > 0)
+    hipLaunchKernelGGL((k_wall<2, T, TAN>), wgrid, block, 0, stream, C, B, p, t1);
+  mark(2);
+  return hipGetLastError();
+}
+
+template <class T>
+static hipError_t fused_pair2_m(const KParams& p, const FusedBufs& fb, long long n,
+                                hipStream_t stream, hipEvent_t* ev) {
+  auto* a = static_cast<const T*>(fb.A);
+  auto* b = static_cast<T*>(fb.B);
+  auto* c = static_cast<T*>(fb.C);
+  const bool half = p.scheme == kHalfWay;
+  if (p.wall_data) {
+    return half ? fused_pair2_t<T, true, true>(p, a, b, c, n, stream, ev)
+                : fused_pair2_t<T, true, false>(p, a, b, c, n, stream, ev);
+  }
+  return half ? fused_pair2_t<T, false, true>(p, a, b, c, n, stream, ev)
+              : fused_pair2_t<T, false, false>(p, a, b, c, n, stream, ev);
+}
+
 hipError_t launch_fused_pair(const KParams& p, int mode, const FusedBufs& fb, long long n,
                              hipStream_t stream, hipEvent_t* ev) {
+  if (p.d == 2) {
+    if (mode == kFP32) return fused_pair2_m<float>(p, fb, n, stream, ev);
+    if (mode == kFP64) return fused_pair2_m<double>(p, fb, n, stream, ev);
+    return hipErrorInvalidValue;
+  }
   if (p.d != 3) return hipErrorInvalidValue;
   if (mode == kFP32) return fused_pair_m<float>(p, fb, n, stream, ev);
   if (mode == kFP64) return fused_pair_m<double>(p, fb, n, stream, ev);

@@ -186,6 +186,38 @@ def test_two_step_passes_equal_single_steps_bitwise(dims, bc, wall_data, precisi
         b.close()
 
 
+@pytest.mark.parametrize("dims,bc,wall_data", [
+    ((261, 37), ["periodic"] * 2, "jets"),
+    ((77, 41), ["fullway"] * 2, "jets"),
+    ((76, 40), ["halfway"] * 2, "jets"),
+    ((300, 19), ["periodic", "fullway"], "jets"),
+    ((600, 21), ["fullway", "periodic"], "jets"),
+    ((70, 30), ["halfway"] * 2, "tangential"),
+    ((3, 2), ["fullway"] * 2, "jets"),
+    ((520, 700), ["fullway"] * 2, "jets"),
+])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_two_step_passes_d2_equal_single_steps_bitwise(dims, bc, wall_data, precision):
+    """d = 2: the same check for the row-marching two-step pass (several tiles
+    along x_1, ragged row chunks, walls on either axis)."""
+    spec = inputs.random_cosines(2, [0.1, -0.15], 0.7, seed=73, kmax=1.0)
+    dx = 1.0 / max(dims[0] - 1, 1)
+    from paper_2410_13165_amd import Lattice
+    a = gpu_lattice(2, dims, dx, spec, bc=bc, precision=precision, wall_data=wall_data)
+    b = Lattice(2, dims, 0.5, dx=dx, u=spec["u"], R=spec.get("R", 0.0), bc=bc, P=4, K=3,
+                precision=precision, field=spec, wall_data=wall_data, steps_per_pass=1)
+    try:
+        assert a.info()["steps_per_pass"] == 2 and b.info()["steps_per_pass"] == 1
+        print(f"[fused2d] dims={dims} bc={bc} {wall_data} {precision}", flush=True)
+        for n in (2, 5, 14):
+            a.step(n)
+            b.step(n)
+            assert torch.equal(_node_state(a), _node_state(b)), n
+    finally:
+        a.close()
+        b.close()
+
+
 def test_two_step_profile_counts_passes():
     spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0, seed=72, kmax=1.0)
     lat = gpu_lattice(3, (40, 30, 20), 1.0 / 39, spec, bc=["fullway"] * 3, precision="fp32")
