@@ -222,6 +222,36 @@ def run_fixed_error(target=1e-6, sizes=(64, 96, 128, 192, 256, 384, 512)):
     return {"target_rmse": target, "t_final": T, "modes": out}
 
 
+def run_d2q9(n=2048):
+    """D2Q9 periodic plane wave phi0 = sin(2 pi x) sin(2 pi y), u = (0.1, 0.2),
+    tau = 1/2, n^2 nodes, n steps (t = 1): MLUPS with two steps per bulk pass and
+    with one, and the RMSE against the transported exact solution."""
+    import torch
+    from paper_2410_13165_amd import Lattice, inputs
+    spec = inputs.plane_sine(2, [0.1, 0.2])
+    out = {"workload": f"D2Q9 {n}^2 periodic, sin(2 pi x) sin(2 pi y), u=(0.1,0.2), {n} steps"}
+    for prec in ("fp64", "fp32"):
+        for spp in (2, 1):
+            lat = Lattice(2, (n, n), 0.5, dx=1.0 / n, u=spec["u"], precision=prec, field=spec,
+                          steps_per_pass=spp)
+            try:
+                lat.step(4)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lat.step(n)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                rmse = lat.diagnostics()["rmse"]
+            finally:
+                lat.close()
+                torch.cuda.empty_cache()
+            out[f"{prec}_pass{spp}"] = {"mlups": round(n * n * n / sec / 1e6, 1),
+                                        "rmse": float(f"{rmse:.4g}")}
+            print(f"# d2q9 {prec} steps/pass {spp}: {n * n * n / sec / 1e6:.0f} MLUPS, "
+                  f"rmse {rmse:.3e}", file=sys.stderr, flush=True)
+    return out
+
+
 def run_sweep(steps=None, count=None, precision="fp32"):
     """512 independent D2Q9 lattices advanced together (tuned launch form);
     per-instance growth of the L2 norm of phi."""
@@ -305,6 +335,7 @@ def main(argv=None):
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-fixed-error", action="store_true")
+    ap.add_argument("--no-d2q9", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args(argv)
@@ -342,6 +373,7 @@ def main(argv=None):
     fixed = None
     if not args.no_fixed_error:
         fixed = run_fixed_error()
+    d2q9 = None if args.no_d2q9 else run_d2q9()
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep()
@@ -410,6 +442,7 @@ def main(argv=None):
                       for k, v in r.items()}
                   for m, r in results.items()},
         "fixed_error": fixed,
+        "d2q9": d2q9,
         "sweep": sweep,
         "adjoint_fwd_ratio": round(adj["ratio"], 4) if adj else None,
         "adjoint": ({k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in adj.items()}
