@@ -882,6 +882,10 @@ struct lbm_batch {
   BatchTile* d_tiles = nullptr;
   int max_tiles = 0, ntiles = 0;
   int tx = 64, ty = 4;
+  // two-step passes (d = 2, every instance with steps_per_pass = 2)
+  bool pairs = false;
+  BatchTile2* d_tiles2 = nullptr;
+  int ntiles2 = 0;
   int cur = 0;
   int64_t step = 0;
   std::string err;
@@ -912,6 +916,43 @@ int batch_tiles(lbm_batch* b, int tx, int ty) {
   return LBM_OK;
 }
 
+// Tile table of the two-step passes (d = 2): every instance cut into x_1
+// tiles of the pass's width and chunks of rows, 64 rows halved (down to 8)
+// while the table has fewer than four tiles per CU.
+int batch_pair_tiles(lbm_batch* b) {
+  bool all = b->d == 2;
+  for (lbm_handle* h : b->inst) all = all && h->steps_per_pass == 2;
+  if (!all) return LBM_OK;
+  const int tw = batch_pair_tile_width(b->precision);
+  auto count = [&](int yc) {
+    long long c = 0;
+    for (lbm_handle* h : b->inst)
+      c += static_cast<long long>((h->kp.n[0] + tw - 1) / tw) * ((h->kp.n[1] + yc - 1) / yc);
+    return c;
+  };
+  int yc = 64;
+  while (yc > 8 && count(yc) < 4 * 256) yc /= 2;
+  if (count(yc) > std::numeric_limits<int32_t>::max())
+    return bfail(b, LBM_EINVAL, "too many tiles in the batch");
+  std::vector<BatchTile2> t;
+  t.reserve(static_cast<size_t>(count(yc)));
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    const KParams& kp = b->inst[i]->kp;
+    for (int y = 0; y < kp.n[1]; y += yc)
+      for (int x = 0; x < kp.n[0]; x += tw)
+        t.push_back(BatchTile2{static_cast<int>(i), x, y, std::min(y + yc, kp.n[1])});
+  }
+  b->d_tiles2 = static_cast<BatchTile2*>(dev_alloc(b->owner, sizeof(BatchTile2) * t.size()));
+  if (!b->d_tiles2) return bfail(b, LBM_ENOMEM, "batch tables");
+  hipError_t e = hipMemcpyAsync(b->d_tiles2, t.data(), sizeof(BatchTile2) * t.size(),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("tile upload: ") + hipGetErrorString(e));
+  b->ntiles2 = static_cast<int>(t.size());
+  b->pairs = true;
+  return LBM_OK;
+}
+
 int batch_upload(lbm_batch* b) {
   std::vector<KParams> kps(b->inst.size());
   std::vector<void*> bufs(2 * b->inst.size());
@@ -930,9 +971,22 @@ int batch_upload(lbm_batch* b) {
   return LBM_OK;
 }
 
-int batch_run(lbm_batch* b, int64_t n) {
+int batch_run(lbm_batch* b, int64_t n, bool allow_pairs = true) {
   if (n <= 0) return LBM_OK;
-  for (int64_t done = 0; done < n;) {
+  int64_t done = 0;
+  if (allow_pairs && b->pairs) {
+    for (int64_t np = n / 2; np > 0;) {
+      const int chunk = static_cast<int>(std::min<int64_t>(np, 1 << 20));
+      hipError_t e = launch_batch_pair(b->d_kps, b->d_bufs, b->d_tiles2, b->ntiles2,
+                                       b->precision, b->cur, chunk, b->stream);
+      if (e != hipSuccess)
+        return bfail(b, LBM_EDEVICE, std::string("batch two-step pass: ") + hipGetErrorString(e));
+      b->cur = (b->cur + chunk) & 1;
+      np -= chunk;
+      done += 2 * static_cast<int64_t>(chunk);
+    }
+  }
+  while (done < n) {
     const int chunk = static_cast<int>(std::min<int64_t>(n - done, 1 << 20));
     hipError_t e = launch_batch(b->d, b->d_kps, b->d_bufs, b->d_tiles, b->ntiles, b->tx, b->ty,
                                 b->precision, b->cur, chunk, b->stream);
@@ -969,6 +1023,7 @@ int lbm_batch_create(int count, int d, const int64_t* dims, const double* tau,
       dev_free(b->owner, b->d_kps);
       dev_free(b->owner, b->d_bufs);
       dev_free(b->owner, b->d_tiles);
+      dev_free(b->owner, b->d_tiles2);
     }
     delete b;
     g_create_error = msg;
@@ -1001,6 +1056,7 @@ int lbm_batch_create(int count, int d, const int64_t* dims, const double* tau,
     return abort_create(bfail(nullptr, LBM_ENOMEM, "batch tables"));
   int rc = batch_upload(b);
   if (rc == LBM_OK) rc = batch_tiles(b, 64, 4);
+  if (rc == LBM_OK) rc = batch_pair_tiles(b);
   if (rc != LBM_OK) {
     g_create_error = b->err;
     return abort_create(rc);
@@ -1070,10 +1126,10 @@ int lbm_batch_tune(lbm_batch* b, int trial_steps, int32_t* config_out, double* m
   for (const Cand& c : cands) {
     rc = batch_tiles(b, c.tx, c.ty);
     if (rc != LBM_OK) break;
-    rc = batch_run(b, 1);  // warm-up
+    rc = batch_run(b, 1, false);  // warm-up
     if (rc != LBM_OK) break;
     (void)hipEventRecord(e0, b->stream);
-    rc = batch_run(b, trial_steps);
+    rc = batch_run(b, trial_steps, false);
     (void)hipEventRecord(e1, b->stream);
     if (rc != LBM_OK) break;
     if (hipEventSynchronize(e1) != hipSuccess) {
@@ -1136,6 +1192,7 @@ int lbm_batch_destroy(lbm_batch* b) {
     dev_free(b->owner, b->d_kps);
     dev_free(b->owner, b->d_bufs);
     dev_free(b->owner, b->d_tiles);
+    dev_free(b->owner, b->d_tiles2);
   }
   for (lbm_handle* h : b->inst) lbm_destroy(h);
   delete b;

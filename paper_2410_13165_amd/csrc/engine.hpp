@@ -79,6 +79,13 @@ struct BatchTile {
   int row0;
 };
 
+// Tile of a batched two-step pass (d = 2): instance, first x_1 node, output
+// rows y0 .. y1 - 1.
+struct BatchTile2 {
+  int inst;
+  int x0, y0, y1;
+};
+
 struct LaunchShape {
   int tx, ty;
   unsigned blocks;
@@ -135,6 +142,13 @@ hipError_t launch_sum_phi0(const KParams& p, const double* arr, double* partial,
 hipError_t launch_batch(int d, const KParams* kps, void* const* bufs, const BatchTile* tiles,
                         int ntiles, int tx, int ty, int mode, int cur, int nsteps,
                         hipStream_t stream);
+
+// npairs two-step passes of every instance of a d = 2 batch (float32 or
+// float64), one launch per pair over the BatchTile2 table.
+hipError_t launch_batch_pair(const KParams* kps, void* const* bufs, const BatchTile2* tiles,
+                             int ntiles, int mode, int cur, int npairs, hipStream_t stream);
+// x_1 width of the tiles of launch_batch_pair
+int batch_pair_tile_width(int mode);
 
 // Adjoint step lambda^{n+1} -> lambda^n (adjoint.hip).  g: forward state at
 // step n (nullable); when given, per-block partial sums of

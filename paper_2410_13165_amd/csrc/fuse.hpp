@@ -100,7 +100,9 @@ __device__ __forceinline__ int adj_slot(int it) {
 // planes replaced by rows).  The c_2 classes of D2Q9 have three members each.
 template <class T, bool HALF>
 struct FuseShape2 {
-  static constexpr int TX = 254, NT = 256, SLOTS = HALF ? 21 : 18;
+  // 256 outputs (lattice sizes are often multiples); threads 0 and 1 also
+  // take the two halo nodes of the step-1 row
+  static constexpr int TX = 256, NT = 256, SLOTS = HALF ? 21 : 18;
 };
 
 constexpr int cy_index(int k) {

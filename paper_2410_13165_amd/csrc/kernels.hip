@@ -714,29 +714,25 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
 // x_2 rows and marches along x_2 (rows play the part of the planes of
 // k_fused2, with no halo across x_2 besides the marching itself).  Rows on a
 // Dirichlet wall of x_2 go through C as in k_fused2.
+// One tile (x_1 nodes x0 .. x0 + TX - 1, output rows yc0 .. yend - 1) of the
+// d = 2 two-step pass; lds holds the block's SLOTS x (TX + 2) row-slots.
 template <class T, bool HALF>
-__global__ void __launch_bounds__(256)
-    k_fused2_d2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p,
-                const int yc) {
+__device__ __forceinline__ void fused2_d2_tile(const T* __restrict__ A, T* __restrict__ B,
+                                               T* __restrict__ C, const KParams& p, T* lds,
+                                               const int x0, const int yc0, const int yend) {
   using S = FuseShape2<T, HALF>;
   constexpr int D = 2, Q = q_of(2), TX = S::TX, NT = S::NT;
   constexpr int R = TX + 2;
-  static_assert(R == NT, "one region node per thread");
-  extern __shared__ __align__(16) unsigned char fuse_lds[];
-  T* lds = reinterpret_cast<T*>(fuse_lds);
+  static_assert(TX == NT, "one output node per thread");
   const long long ps = p.pstride;
   const int n0 = p.n[0], n1 = p.n[1];
-  int tx_, ty_;
-  fuse_tile2(p, TX, tx_, ty_);
-  const int x0 = tx_ * TX, yc0 = ty_ * yc;
-  const int yend = min(yc0 + yc, n1);
   const int iters = yend - yc0 + 2;
   const int r = threadIdx.x;
   for (int it = 0; it < iters; ++it) {
     const int yp = yc0 - 1 + it;  // step-1 row of this iteration
     // ---- step 1 on the tile and its halo of row yp
-    {
-      int gx = x0 - 1 + r, gy = yp;
+    for (int rr = r; rr < R; rr += NT) {
+      int gx = x0 - 1 + rr, gy = yp;
       bool skip = false;
       if (gx < 0 || gx >= n0) {
         if (p.bc[0] != 0) skip = true;
@@ -780,7 +776,7 @@ __global__ void __launch_bounds__(256)
           collide_vals<D, T>(f, p);
           // rows next to a wall of x_2, owned by this block: kept for the
           // step-2 wall kernel
-          const bool own = r >= 1 && r <= TX && x0 - 1 + r < n0 && yp >= yc0 && yp < yend;
+          const bool own = rr >= 1 && rr <= TX && x0 - 1 + rr < n0 && yp >= yc0 && yp < yend;
           const bool near = p.bc[1] != 0 && (ri.i[1] == 1 || ri.i[1] == n1 - 2);
           if (own && near) {
 #pragma unroll
@@ -789,7 +785,7 @@ __global__ void __launch_bounds__(256)
         }
         static_for<0, Q>([&](auto K) {
           constexpr int k = decltype(K)::value;
-          lds[fuse_slot2<HALF, k>(it) * R + r] = f[k];
+          lds[fuse_slot2<HALF, k>(it) * R + rr] = f[k];
         });
       }
     }
@@ -835,6 +831,31 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
   }
+}
+
+template <class T, bool HALF>
+__global__ void __launch_bounds__(256)
+    k_fused2_d2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p,
+                const int yc) {
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  int tx_, ty_;
+  fuse_tile2(p, FuseShape2<T, HALF>::TX, tx_, ty_);
+  const int yc0 = ty_ * yc;
+  fused2_d2_tile<T, HALF>(A, B, C, p, reinterpret_cast<T*>(fuse_lds),
+                          tx_ * FuseShape2<T, HALF>::TX, yc0, min(yc0 + yc, p.n[1]));
+}
+
+// Two steps of many periodic d = 2 lattices in one launch: block b takes tile
+// tiles[b] (instance, x_1 start, row range) with the instance's parameter
+// block and buffers (cur selects the source).
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_fused2_d2_batch(const KParams* __restrict__ kps, T* const* __restrict__ bufs,
+                      const BatchTile2* __restrict__ tiles, const int cur) {
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  const BatchTile2 t = tiles[blockIdx.x];
+  fused2_d2_tile<T, false>(bufs[2 * t.inst + cur], bufs[2 * t.inst + 1 - cur], nullptr,
+                           kps[t.inst], reinterpret_cast<T*>(fuse_lds), t.x0, t.y0, t.y1);
 }
 
 // Many lattices in one launch (periodic instances): block b updates rows
@@ -1755,6 +1776,41 @@ static hipError_t batch_d(const KParams* kps, void* const* bufs, const BatchTile
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <class T>
+static hipError_t batch_pair_t(const KParams* kps, void* const* bufs, const BatchTile2* tiles,
+                               int ntiles, int cur, int npairs, hipStream_t stream) {
+  using S = FuseShape2<T, false>;
+  constexpr size_t lds = sizeof(T) * S::SLOTS * (S::TX + 2);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused2_d2_batch<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  for (int i = 0; i < npairs; ++i) {
+    // a two-step pass reads buffer c and writes buffer 1 - c, as one step does
+    const int c = (cur + i) & 1;
+    hipLaunchKernelGGL((k_fused2_d2_batch<T>), dim3(ntiles), dim3(S::NT), lds, stream, kps,
+                       reinterpret_cast<T* const*>(bufs), tiles, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_batch_pair(const KParams* kps, void* const* bufs, const BatchTile2* tiles,
+                             int ntiles, int mode, int cur, int npairs, hipStream_t stream) {
+  if (mode == kFP64) return batch_pair_t<double>(kps, bufs, tiles, ntiles, cur, npairs, stream);
+  if (mode == kFP32) return batch_pair_t<float>(kps, bufs, tiles, ntiles, cur, npairs, stream);
+  return hipErrorInvalidValue;
+}
+
+int batch_pair_tile_width(int mode) {
+  return mode == kFP64 ? FuseShape2<double, false>::TX : FuseShape2<float, false>::TX;
 }
 
 hipError_t launch_batch(int d, const KParams* kps, void* const* bufs, const BatchTile* tiles,

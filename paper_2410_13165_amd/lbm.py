@@ -449,7 +449,8 @@ class _BatchMember(Lattice):
 class Batch:
     """Independent periodic lattices of one d and precision advanced together.
 
-    specs: list of dicts with keys dims, tau, dx, u and optional R, m4, g.
+    specs: list of dicts with keys dims, tau, dx, u and optional R, m4, g, K and
+    steps_per_pass (2 by default: d = 2 batches advance two steps per pass).
     """
 
     def __init__(self, d: int, specs, precision: str = "fp32", device=None):
@@ -494,6 +495,7 @@ class Batch:
                 p.m4 = float(sp["m4"])
                 p.use_m4 = 1
             p.init_order = int(sp.get("K", 1))
+            p.steps_per_pass = int(sp.get("steps_per_pass", 2))
             p.precision = PRECISION[precision]
             p.alloc = self._alloc_cb
             p.free_fn = self._free_cb

@@ -76,6 +76,31 @@ def test_tuner_restores_state_and_configs_agree():
             assert torch.equal(a.instance(i).phi(), b.instance(i).phi()), i
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_two_step_passes_equal_single_steps(precision):
+    """d = 2 batches advance two steps per pass (one launch over a table of
+    (instance, x_1 tile, row chunk)); the populations are bitwise those of the
+    single-step batch, odd step counts included."""
+    from paper_2410_13165_amd import Batch
+    rng = np.random.default_rng(45)
+    specs = _specs(rng, 11, [16, 64, 300, 520], (0.5, 1.6), (-0.4, 0.4))
+    single = [dict(sp, steps_per_pass=1) for sp in specs]
+    parts, phi0 = _concat_phi0(specs, 800)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    with Batch(2, specs, precision=precision) as a, Batch(2, single, precision=precision) as b:
+        a.set_initial(phi0)
+        b.set_initial(phi0)
+        for n in (2, 7, 16):
+            a.step(n)
+            b.step(n)
+            for i in range(len(specs)):
+                ia, ib = a.instance(i).info(), b.instance(i).info()
+                assert ia["steps_per_pass"] == 2 and ib["steps_per_pass"] == 1
+                sa = a.instance(i).get_state().view(dt).reshape(ia["q"], ia["pstride"])
+                sb = b.instance(i).get_state().view(dt).reshape(ib["q"], ib["pstride"])
+                assert torch.equal(sa[:, : ia["nodes"]], sb[:, : ib["nodes"]]), (n, i)
+
+
 def test_batch_rejects_stepping_an_instance():
     from paper_2410_13165_amd import Batch, LbmError
     specs = [{"dims": (16, 16), "tau": 0.5, "u": [0.1, 0.1], "dx": 1 / 16}]
