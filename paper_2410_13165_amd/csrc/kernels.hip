@@ -677,20 +677,26 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
         if (ri.rowwall) continue;
         col_setup<D>(p, gx, ri);
         const int node = ri.rowbase + gx;
+        // every pull from LDS, then the x_1-face unknowns from B's row slots
+        // in a branch of their own (a per-lane choice between the two would
+        // become one generic-pointer load, which waits on all memory traffic)
         T f[Q];
         static_for<0, Q>([&](auto K) {
           constexpr int k = decltype(K)::value;
           constexpr Vec4i c = vel_vec(D, k);
           constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
-          bool face = false;
-          if constexpr (c.v[0] != 0) face = (c.v[0] == 1) ? ri.lo[0] : ri.hi[0];
-          if (face) {
-            f[k] = B[k * ps + p.xoff + row];
-          } else {
-            const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
-            f[k] = lds[fuse_slot<HALF, k>(it - src_it) * R + rr];
-          }
+          const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
+          f[k] = lds[fuse_slot<HALF, k>(it - src_it) * R + rr];
         });
+        if (ri.lo[0] || ri.hi[0]) {
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] = B[k * ps + p.xoff + row];
+            }
+          });
+        }
         if (HALF && (ri.lo[0] || ri.hi[0])) {
           const int own = (oy + 1) * RX + (ox + 1);
           static_for<0, Q>([&](auto K) {
@@ -801,19 +807,23 @@ __device__ __forceinline__ void fused2_d2_tile(const T* __restrict__ A, T* __res
         if (!ri.rowwall) {
           col_setup<D>(p, gx, ri);
           const int node = ri.rowbase + gx;
+          // pulls from LDS, x_1-face unknowns from B's row slots (as k_fused2)
           T f[Q];
           static_for<0, Q>([&](auto K) {
             constexpr int k = decltype(K)::value;
             constexpr Vec4i c = vel_vec(D, k);
             constexpr int src_it = c.v[1] == 0 ? 1 : (c.v[1] == 1 ? 2 : 0);
-            bool face = false;
-            if constexpr (c.v[0] != 0) face = (c.v[0] == 1) ? ri.lo[0] : ri.hi[0];
-            if (face) {
-              f[k] = B[k * ps + p.xoff + row];
-            } else {
-              f[k] = lds[fuse_slot2<HALF, k>(it - src_it) * R + (r + 1 - c.v[0])];
-            }
+            f[k] = lds[fuse_slot2<HALF, k>(it - src_it) * R + (r + 1 - c.v[0])];
           });
+          if (ri.lo[0] || ri.hi[0]) {
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] = B[k * ps + p.xoff + row];
+              }
+            });
+          }
           if (HALF && (ri.lo[0] || ri.hi[0])) {
             static_for<0, Q>([&](auto K) {
               constexpr int k = decltype(K)::value;
