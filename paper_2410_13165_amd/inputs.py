@@ -100,7 +100,8 @@ ADJOINT_D3Q19 = {"d": 3, "n": 256, "u": [0.05, 0.1, 0.08], "steps": 1000, "every
 
 # Stability sweep: 512 independent periodic D2Q9 lattices, sizes drawn from
 # {64^2, 128^2, 256^2, 512^2}, tau ~ U(0.5, 2.0), sigma ~ U(-0.75, 0.75)^2
-# (straddling the |sigma| < 1/2 region), R = 0, K = 1, noise N(0, 1e-6), 4000 steps.
+# (straddling the |sigma| < 1/2 region), R = 0, K = 1, noise of standard deviation
+# 1e-3, 4000 steps.
 SWEEP_D2Q9 = {"count": 512, "sizes": [64, 128, 256, 512], "tau": (0.5, 2.0),
               "sigma": (-0.75, 0.75), "std": 1e-3, "steps": 4000, "seed": 4}
 

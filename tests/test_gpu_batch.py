@@ -144,3 +144,31 @@ def test_stability_sweep_matches_spectral_radius():
             assert growth[i] < 1.2, (i, rho, growth[i])
         if sp["tau"] == 0.5 and abs(infos[i]["min_omega"]) > 1e-2:
             assert (infos[i]["min_omega"] > 0) == (rho < 1 + 1e-9), (i, rho)
+
+
+def test_sweep_workload_full_size():
+    """The stability-sweep workload at full size (512 D2Q9 instances of
+    64^2..512^2, tau and u per instance, N(0, 1e-3) noise), in the benchmark's
+    launch form (tuned block shape, two steps per pass, then one single step):
+    after 5 steps one instance of each grid size against its own oracle run."""
+    from paper_2410_13165_amd import Batch
+    specs = inputs.sweep_specs()
+    phi0 = inputs.sweep_phi0(specs)
+    offs = np.concatenate([[0], np.cumsum([int(np.prod(sp["dims"])) for sp in specs])])
+    picks = {}
+    for i, sp in enumerate(specs):
+        picks.setdefault(sp["dims"][0], i)
+    steps = 5
+    with Batch(2, specs, precision="fp32") as b:
+        b.set_initial(torch.from_numpy(phi0))
+        b.tune(2)
+        b.step(steps)
+        for n, i in sorted(picks.items()):
+            sp = specs[i]
+            print(f"[sweep] instance {i} dims={sp['dims']} tau={sp['tau']:.3f}", flush=True)
+            prob = oracle_problem(2, sp["dims"], sp["dx"], None, u=sp["u"], tau=sp["tau"],
+                                  K=sp["K"])
+            part = phi0[offs[i]:offs[i + 1]].reshape(tuple(reversed(sp["dims"])))
+            run = O.Run(prob, phi0=to_oracle_order(part)).step(steps)
+            got = to_oracle_order(b.instance(i).phi().cpu().numpy())
+            assert rel_l2(got, run.phi()) <= 2e-5, (i, sp)

@@ -387,16 +387,20 @@ def test_zero_steps_and_error_reporting():
 
 # ------------------------------------------------------- full-size check ---
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_benchmark_configuration_sampled(precision):
-    """D3Q19, 512^3 nodes, full-way walls on all faces, the benchmark's launch
-    configuration: after r steps, phi at sampled nodes (interior, faces, edges,
-    corners) against oracle runs on the sub-boxes of radius r around them."""
+@pytest.mark.parametrize("precision,scheme", [("fp32", "fullway"), ("fp64", "fullway"),
+                                              ("fp32_split", "fullway"), ("fp32", "halfway"),
+                                              ("fp64", "halfway")])
+def test_benchmark_configuration_sampled(precision, scheme):
+    """D3Q19, 512^3 nodes, full-way (the benchmark) or half-way walls on all
+    faces, in the benchmark's launch configuration (a two-step pass, then one
+    single step): after r = 3 steps, phi at sampled nodes (interior, faces,
+    edges, corners) against oracle runs on the sub-boxes of radius r around
+    them."""
     w = inputs.BENCH_D3Q19
     n, r = w["n"], 3
     spec = inputs.bench_field()
-    dx = 1.0 / (n - 1)
-    bc = ["fullway"] * 3
+    dx = 1.0 / (n - 1) if scheme == "fullway" else 1.0 / n
+    bc = [scheme] * 3
     lat = gpu_lattice(3, (n, n, n), dx, spec, bc=bc, precision=precision)
     try:
         lat.step(r)
@@ -409,7 +413,36 @@ def test_benchmark_configuration_sampled(precision):
         for idx in samples:
             want = local_oracle_phi(3, (n, n, n), dx, spec, bc, idx, r)
             got = float(phi[idx[2], idx[1], idx[0]])
-            print(f"[sample] {precision} {idx} got={got:.15g} want={want:.15g}", flush=True)
+            print(f"[sample] {precision} {scheme} {idx} got={got:.15g} want={want:.15g}",
+                  flush=True)
+            assert abs(got - want) <= tol * max(1.0, abs(want)), idx
+    finally:
+        lat.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_d2q9_2048_sampled(precision):
+    """D2Q9 2048^2 periodic, the plane-wave workload of the grid-refinement
+    study at its finest grid, in the benchmark's launch configuration (two
+    steps per pass for d = 2, then one single step): after r = 5 steps, phi at
+    sampled nodes against oracle runs on the sub-boxes of radius r."""
+    n, r = 2048, 5
+    spec = inputs.plane_sine(2, [0.1, 0.2])
+    dx = 1.0 / n
+    bc = ["periodic"] * 2
+    lat = gpu_lattice(2, (n, n), dx, spec, bc=bc, precision=precision)
+    try:
+        assert lat.info()["steps_per_pass"] == 2
+        lat.step(r)
+        phi = lat.phi()  # (y, x)
+        rng = np.random.default_rng(6)
+        samples = [(r, r), (n - 1 - r, n - 1 - r), (1023, 1024), (255, 1790)]
+        samples += [tuple(int(v) for v in rng.integers(r, n - r, 2)) for _ in range(8)]
+        tol = TOL[precision]
+        for idx in samples:
+            want = local_oracle_phi(2, (n, n), dx, spec, bc, idx, r)
+            got = float(phi[idx[1], idx[0]])
+            print(f"[sample] d2q9 {precision} {idx} got={got:.15g} want={want:.15g}", flush=True)
             assert abs(got - want) <= tol * max(1.0, abs(want)), idx
     finally:
         lat.close()
