@@ -16,7 +16,8 @@ in LDS): its algorithmic bytes per launch (2 q sizeof(float) per node of the
 average duration from HIP events recorded around every launch on the
 library's stream during the timed region.  Because the two-step kernel moves
 fewer bytes than two single steps, the measured HBM traffic (from the
-committed counter profile) is reported beside it.  The CPU baseline is the
+committed counter profile) is reported beside it, with the bandwidth of a plain
+device copy measured in the same run.  The CPU baseline is the
 float64 oracle on a bounded sample of the same workload.
 
 Prints one JSON line.
@@ -321,6 +322,27 @@ def cpu_baseline(n_sample: int, steps: int):
     }
 
 
+def measure_copy_gbs(gib: float = 2.0, reps: int = 10) -> float:
+    """Bandwidth of a plain device-to-device copy (torch's copy kernel) of `gib`
+    GiB: bytes read plus bytes written per launch over the mean duration."""
+    import torch
+    nbytes = int(gib * (1 << 30))
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / sec / 1e9
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,6 +384,9 @@ def main(argv=None):
         print(f"# calibration copy: {nbytes} bytes read and written per launch", file=sys.stderr)
         del a, b
         torch.cuda.empty_cache()
+
+    copy_gbs = measure_copy_gbs()
+    print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     results = {}
@@ -406,9 +431,12 @@ def main(argv=None):
         "bytes_per_launch": head["bulk_bytes_per_launch"],
         "avg_launch_ms": round(head["bulk_ms"], 4),
     }
+    # a plain device copy measured in the same process, for scale
+    roofline["copy_gbs_measured"] = round(copy_gbs, 1)
     if traffic:
         # measured HBM bytes per launch over the same duration
         roofline["hbm_gbs_measured"] = round(traffic / (head["bulk_ms"] / 1e3) / 1e9, 1)
+        roofline["hbm_frac_of_copy"] = round(roofline["hbm_gbs_measured"] / copy_gbs, 4)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_nodes, args.cpu_steps)

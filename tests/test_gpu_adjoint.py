@@ -208,11 +208,14 @@ def test_autograd_function_matches_finite_differences():
 
 
 @pytest.mark.parametrize("prec,bc,tol", [("fp64", "fullway", 1e-12), ("fp64", "halfway", 1e-12),
+                                         ("fp64", "periodic", 1e-12),
                                          ("fp32", "periodic", 2e-6),
+                                         ("fp32_split", "periodic", 2e-6),
                                          ("fp32_split", "fullway", 2e-6)])
 def test_two_step_adjoint_matches_single_steps(prec, bc, tol):
     """d = 3: the replay and the adjoint advanced two steps per pass give the
-    gradients of the single-step passes (to rounding of the reduction order)."""
+    gradients of the single-step passes (to rounding of the reduction order);
+    segments of 6 and 5 steps cover even and odd lengths."""
     from paper_2410_13165_amd import Lattice
     d, dims = 3, (40, 30, 37)
     spec = inputs.random_cosines(3, [0.05, -0.1, 0.08], 0.4, seed=77, kmax=1.0)
