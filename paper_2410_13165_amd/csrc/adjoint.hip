@@ -230,7 +230,8 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
   for (int it = 0; it < iters; ++it) {
     const int zp = zc0 - 1 + it;
     // ---- lambda^n on the tile and its halo of plane zp
-    for (int r = threadIdx.x; r < R; r += NT) {
+    for (int t = threadIdx.x; t < R; t += NT) {
+      const int r = fuse_region<TX, TY>(t);
       const int rx = r % RX, ry = r / RX;
       int gx = x0 - 1 + rx, gy = y0 - 1 + ry, gz = zp;
       if (gx < 0 || gx >= n0) {

@@ -67,6 +67,19 @@ __device__ __forceinline__ int fuse_wrap(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// Region index (ry * (TX + 2) + rx, the tile and its halo of one) of phase-1
+// work item t in [0, (TX + 2)(TY + 2)): the first TX * (TY + 2) items run along
+// the interior columns 1..TX of each region row, so a wavefront's loads start
+// on the tile's aligned x_1 origin instead of straddling two region rows; the
+// last 2 (TY + 2) items are the halo columns 0 and TX + 1.  A bijection.
+template <int TX, int TY>
+__device__ __forceinline__ int fuse_region(int t) {
+  constexpr int RX = TX + 2, RY = TY + 2;
+  if (t < TX * RY) return (t / TX) * RX + 1 + t % TX;
+  const int h = t - TX * RY;
+  return (h >> 1) * RX + ((h & 1) ? TX + 1 : 0);
+}
+
 // Tile of this block.  Workgroups go to the 8 XCDs round-robin by index, so
 // block b is given tile (b mod 8) * per + b / 8: each XCD walks a contiguous
 // run of tiles in x_1-fastest order, and the tiles next to each other in x_1

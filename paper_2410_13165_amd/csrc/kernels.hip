@@ -601,7 +601,8 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
   for (int it = 0; it < iters; ++it) {
     const int zp = zc0 - 1 + it;  // step-1 plane of this iteration
     // ---- step 1 on the tile and its halo of plane zp
-    for (int r = threadIdx.x; r < R; r += NT) {
+    for (int t = threadIdx.x; t < R; t += NT) {
+      const int r = fuse_region<TX, TY>(t);
       const int rx = r % RX, ry = r / RX;
       int gx = x0 - 1 + rx, gy = y0 - 1 + ry, gz = zp;
       if (gx < 0 || gx >= n0) {
@@ -998,6 +999,9 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
   const double dtR = p.dt * p.R;
   for (int it = 0; it < iters; ++it) {
     const int zp = zc0 - 1 + it;
+    // plain region order: with two items per thread the halo-column items of
+    // fuse_region would gather one wavefront's loads from every region row in
+    // the second round, with nothing left to overlap them (measured slower)
     for (int r = threadIdx.x; r < R; r += NT) {
       const int rx = r % RX, ry = r / RX;
       int gx = x0 - 1 + rx, gy = y0 - 1 + ry, gz = zp;
