@@ -385,8 +385,11 @@ def main(argv=None):
         del a, b
         torch.cuda.empty_cache()
 
-    copy_gbs = measure_copy_gbs()
-    print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    # (not in counter-calibration runs, whose only large copies must be the
+    # calibration copies)
+    copy_gbs = measure_copy_gbs() if args.calib_copy_gib <= 0 else None
+    if copy_gbs:
+        print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     results = {}
@@ -432,11 +435,12 @@ def main(argv=None):
         "avg_launch_ms": round(head["bulk_ms"], 4),
     }
     # a plain device copy measured in the same process, for scale
-    roofline["copy_gbs_measured"] = round(copy_gbs, 1)
+    roofline["copy_gbs_measured"] = round(copy_gbs, 1) if copy_gbs else None
     if traffic:
         # measured HBM bytes per launch over the same duration
         roofline["hbm_gbs_measured"] = round(traffic / (head["bulk_ms"] / 1e3) / 1e9, 1)
-        roofline["hbm_frac_of_copy"] = round(roofline["hbm_gbs_measured"] / copy_gbs, 4)
+        if copy_gbs:
+            roofline["hbm_frac_of_copy"] = round(roofline["hbm_gbs_measured"] / copy_gbs, 4)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_nodes, args.cpu_steps)
