@@ -253,6 +253,40 @@ def run_d2q9(n=2048):
     return out
 
 
+def run_d2q9_convergence(sizes=(64, 128, 256, 512, 1024, 2048)):
+    """The grid-refinement study of the D2Q9 plane wave: phi0 = sin(2 pi x)
+    sin(2 pi y), u = (0.1, 0.2), periodic unit square, n^2 nodes and n steps
+    (t = 1), per storage mode at tau = 1/2, plus float64 at one tau drawn from
+    U[0.6, 1.5] (seed 2); RMSE against the transported exact solution and the
+    observed order log2(e_n / e_2n) per grid."""
+    import numpy as np
+    import torch
+    from paper_2410_13165_amd import Lattice, inputs
+    spec = inputs.plane_sine(2, [0.1, 0.2])
+    tau_draw = float(np.random.default_rng(2).uniform(0.6, 1.5))
+    cases = [("fp64", 0.5), ("fp32", 0.5), ("fp32_split", 0.5), ("fp64", tau_draw)]
+    out = {"workload": "D2Q9 periodic plane wave sin(2 pi x) sin(2 pi y), u=(0.1,0.2), "
+                       "n^2 nodes, n steps (t = 1)", "cases": []}
+    for prec, tau in cases:
+        runs = []
+        for n in sizes:
+            lat = Lattice(2, (n, n), tau, dx=1.0 / n, u=spec["u"], precision=prec, field=spec)
+            try:
+                lat.step(n)
+                rmse = lat.diagnostics()["rmse"]
+            finally:
+                lat.close()
+                torch.cuda.empty_cache()
+            order = math.log2(runs[-1]["rmse"] / rmse) if runs and rmse > 0 else None
+            runs.append({"n": n, "rmse": float(f"{rmse:.5g}"),
+                         "order": round(order, 3) if order is not None else None})
+        print(f"# d2q9 convergence {prec} tau={tau:.4f}: " +
+              " ".join(f"{r['n']}:{r['rmse']:.3e}" + (f"({r['order']:.2f})" if r["order"] else "")
+                       for r in runs), file=sys.stderr, flush=True)
+        out["cases"].append({"precision": prec, "tau": tau, "runs": runs})
+    return out
+
+
 def run_sweep(steps=None, count=None, precision="fp32"):
     """512 independent D2Q9 lattices advanced together (tuned launch form);
     per-instance growth of the L2 norm of phi."""
@@ -402,6 +436,7 @@ def main(argv=None):
     if not args.no_fixed_error:
         fixed = run_fixed_error()
     d2q9 = None if args.no_d2q9 else run_d2q9()
+    conv = None if args.no_d2q9 else run_d2q9_convergence()
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep()
@@ -475,6 +510,7 @@ def main(argv=None):
                   for m, r in results.items()},
         "fixed_error": fixed,
         "d2q9": d2q9,
+        "d2q9_convergence": conv,
         "sweep": sweep,
         "adjoint_fwd_ratio": round(adj["ratio"], 4) if adj else None,
         "adjoint": ({k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in adj.items()}

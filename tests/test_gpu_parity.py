@@ -446,3 +446,22 @@ def test_d2q9_2048_sampled(precision):
             assert abs(got - want) <= tol * max(1.0, abs(want)), idx
     finally:
         lat.close()
+
+
+def test_d2q9_fourth_order_convergence_fp64():
+    """The plane-wave refinement study on the GPU (D2Q9, tau = 1/2, float64,
+    64^2 .. 512^2, n steps to t = 1): the error ratio per halving of dx
+    approaches 16, the fourth order of the method under acoustic scaling."""
+    spec = inputs.plane_sine(2, [0.1, 0.2])
+    errs = []
+    for n in (64, 128, 256, 512):
+        lat = gpu_lattice(2, (n, n), 1.0 / n, spec, precision="fp64")
+        try:
+            lat.step(n)
+            errs.append(lat.diagnostics()["rmse"])
+        finally:
+            lat.close()
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    print(f"[convergence] rmse {errs} orders {orders}", flush=True)
+    assert all(o > 3.7 for o in orders), orders
+    assert abs(orders[-1] - 4.0) <= 0.15, orders
