@@ -65,13 +65,19 @@ def committed_traffic(bytes_per_launch: float):
     return float(m_val.group(1))
 
 
-def run_mode(precision: str, steps: int, warmup: int, n: int):
+def run_mode(precision: str, steps: int, warmup: int, n: int, scheme: str = "fullway", u=None):
+    """The benchmark workload in one storage mode; `scheme` / `u` switch to
+    half-way walls (dx = 1/n, cell-centred nodes) and another velocity (the
+    same four cosines, seed 3)."""
     import torch
     from paper_2410_13165_amd import Lattice, inputs
     w = inputs.BENCH_D3Q19
-    spec = inputs.bench_field()
-    lat = Lattice(3, (n, n, n), 0.5, dx=1.0 / (n - 1), u=w["u"], R=w["R"],
-                  bc=["fullway"] * 3, P=4, K=3, precision=precision, field=spec)
+    u = list(w["u"]) if u is None else list(u)
+    spec = inputs.bench_field() if u == list(w["u"]) else inputs.random_cosines(3, u, w["R"],
+                                                                               w["seed"])
+    dx = 1.0 / (n - 1) if scheme == "fullway" else 1.0 / n
+    lat = Lattice(3, (n, n, n), 0.5, dx=dx, u=u, R=w["R"],
+                  bc=[scheme] * 3, P=4, K=3, precision=precision, field=spec)
     try:
         info = lat.info()
         lat.step(warmup)
@@ -392,6 +398,8 @@ def main(argv=None):
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-fixed-error", action="store_true")
     ap.add_argument("--no-d2q9", action="store_true")
+    ap.add_argument("--no-halfway", action="store_true")
+    ap.add_argument("--halfway-steps", type=int, default=200)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args(argv)
@@ -435,6 +443,20 @@ def main(argv=None):
     fixed = None
     if not args.no_fixed_error:
         fixed = run_fixed_error()
+    halfway = None
+    if not args.no_halfway:
+        # half-way walls diverge at the benchmark's u (Table 1's pattern), so
+        # they are timed at u = 1e-3 in every component
+        halfway = {"workload": (f"D3Q19 {args.n}^3 half-way Dirichlet on all faces, same "
+                                "cosines, u=(1e-3,1e-3,1e-3), R=1, tau=1/2, K=3, P=4, "
+                                f"{args.halfway_steps} steps")}
+        for m in ("fp32", "fp64"):
+            r = run_mode(m, args.halfway_steps, 4, args.n, scheme="halfway", u=[1e-3] * 3)
+            halfway[m] = {"mlups": round(r["mlups"], 1), "bulk_gbs": round(r["bulk_gbs"], 1),
+                          "steps_per_launch": r["steps_per_launch"],
+                          "rmse": float(f"{r['rmse']:.4g}")}
+            print(f"# halfway {m}: {r['mlups']:.0f} MLUPS, bulk {r['bulk_gbs']:.0f} GB/s, "
+                  f"rmse {r['rmse']:.3e}", file=sys.stderr, flush=True)
     d2q9 = None if args.no_d2q9 else run_d2q9()
     conv = None if args.no_d2q9 else run_d2q9_convergence()
     sweep = None
@@ -509,6 +531,7 @@ def main(argv=None):
                       for k, v in r.items()}
                   for m, r in results.items()},
         "fixed_error": fixed,
+        "halfway": halfway,
         "d2q9": d2q9,
         "d2q9_convergence": conv,
         "sweep": sweep,
