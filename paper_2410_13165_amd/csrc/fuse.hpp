@@ -9,13 +9,41 @@
 
 namespace lbm {
 
-// x_3 planes per block: 64, halved (down to 16) while the grid has fewer
-// than four blocks per CU, so that small lattices still fill the chip; every
-// chunk recomputes two step-1 planes of its neighbours.
-__host__ __device__ constexpr int fuse_zchunk(int tiles_xy, int n2) {
-  int zc = 64;
-  while (zc > 16 && tiles_xy * ((n2 + zc - 1) / zc) < 4 * 256) zc /= 2;
-  return zc;
+// Compute units of the current device (cached per device; 256 on MI355X).
+inline int device_cus() {
+  static int cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+// x_3 planes per block.  The passes run one block per CU (the LDS holds one
+// tile) and a block of zc planes takes zc + 2 iterations (it recomputes two
+// step-1 planes beyond its own), so the pass takes about
+// ceil(blocks / CUs) * (zc + 2) iteration times with blocks = tiles_xy *
+// ceil(n2 / zc): the chunk is the zc <= 64 that minimises that (the largest
+// on ties).  Large lattices get 64; small ones trade a little recomputation
+// for a last round of blocks that is not nearly empty.
+inline int fuse_zchunk(int tiles_xy, int n2) {
+  const long long cus = device_cus();
+  int best = 64;
+  long long best_cost = -1;
+  for (int zc = 64; zc >= 4; --zc) {
+    const long long blocks = static_cast<long long>(tiles_xy) * ((n2 + zc - 1) / zc);
+    const long long cost = (blocks + cus - 1) / cus * ((zc < n2 ? zc : n2) + 2);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = zc;
+    }
+  }
+  return best;
 }
 
 // Tiles fill most of the 160 KB of LDS with one block per CU: SLOTS planes of
