@@ -258,6 +258,25 @@ __device__ void field_initial(const FieldDev& F, const KParams& p, const double 
 // applied to phi*, plus (dt/2)(R_k + R_kbar), truncated at order P; the new
 // population is that minus the post-collision f*_kbar at x_f.
 
+// The wall kernels of d = 2 and 3 are compiled per variant of the wall
+// formula, V = full-way (bit 0) | cosine field (bit 1; otherwise exponential):
+// a kernel then holds the registers of one variant, not of all four (which
+// left one wavefront per SIMD).  V = -1 takes both from the lattice at run
+// time (d = 1 and 4, to bound the build).
+template <int V>
+__device__ __forceinline__ bool wall_full(const KParams& p) {
+  if constexpr (V < 0) return p.scheme == kFullWay;
+  else return (V & 1) != 0;
+}
+template <int V>
+__device__ __forceinline__ bool wall_cos(const KParams& p) {
+  if constexpr (V < 0) return p.field.kind == kFieldCos;
+  else return (V & 2) != 0;
+}
+inline int wall_variant(const KParams& p) {
+  return (p.scheme == kFullWay ? 1 : 0) | (p.field.kind == kFieldCos ? 2 : 0);
+}
+
 // Analytic wall values at one node (coordinates x) for the step
 // t_n -> t_{n+1}, for every population k with sel(k) true, into val[k]:
 // full-way: eq. (bun-1) at (x, t_{n+1}), the whole pre-collision f_k;
@@ -272,15 +291,15 @@ __device__ void field_initial(const FieldDev& F, const KParams& p, const double 
 // equation: c_k . grad F = alpha . grad_tan F + beta d_t F with
 // alpha = c_k - (c_kj / u_j) u (tangential, alpha_j = 0) and beta = -c_kj / u_j,
 // i.e. the factor alpha . kappa + beta (-kappa . u).
-template <int D, bool TAN, class Sel, class Axis>
+template <int D, bool TAN, int V, class Sel, class Axis>
 __device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x)[kMaxDim],
                                               double t_n, Sel sel, Axis axis,
                                               double (&val)[q_of(D)]) {
   constexpr int Q = q_of(D);
   const FieldDev& F = p.field;
   const double dt = p.dt;
-  const bool full = p.scheme == kFullWay;
-  const bool is_cos = F.kind == kFieldCos;
+  const bool full = wall_full<V>(p);
+  const bool is_cos = wall_cos<V>(p);
   const double o2 = p.P >= 2 ? 1.0 : 0.0;
   const double o3 = p.P >= 3 ? 1.0 : 0.0;
   const double o4 = p.P >= 4 ? 1.0 : 0.0;
@@ -386,7 +405,7 @@ constexpr int xface_slot(int D, int k) {
 // rows that lie on a wall of an axis >= 2 and by the x_1 faces through
 // k_xface).  fstar_local(kb) returns the absolute post-collision f*_kb at the
 // node.
-template <int D, bool TAN, class A, class FStarLocal>
+template <int D, bool TAN, int V, class A, class FStarLocal>
 __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, const RowInfo<D>& r,
                                             double t_n, double ref, FStarLocal fstar_local) {
   double x[kMaxDim] = {0.0, 0.0, 0.0, 0.0};
@@ -403,9 +422,9 @@ __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, c
     ax[k] = TAN ? wall_axis<D, k>(r) : 0;
   });
   double val[q_of(D)];
-  wall_analytic<D, TAN>(p, x, t_n, [&](int k) { return out[k]; }, [&](int k) { return ax[k]; },
-                        val);
-  const bool half = p.scheme == kHalfWay;
+  wall_analytic<D, TAN, V>(p, x, t_n, [&](int k) { return out[k]; },
+                           [&](int k) { return ax[k]; }, val);
+  const bool half = !wall_full<V>(p);
   static_for<0, q_of(D)>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if (!out[k]) return;
@@ -426,7 +445,7 @@ __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, c
 //             stored post-collision kbar value of the node),
 // with ref = phi_ref + R t_{n+1} in float32 mode and 0 otherwise.  The split
 // mode keeps float64 values in p.xdata[(side * (2D-1) + slot) * rows + row].
-template <int D, class T, bool TAN>
+template <int D, class T, bool TAN, int V>
 __global__ void __launch_bounds__(256)
     k_xface(T* __restrict__ buf, const KParams p, const double t_n, const int mode) {
   constexpr int S = 2 * D - 1;
@@ -444,12 +463,12 @@ __global__ void __launch_bounds__(256)
     x[a] = p.origin[a] + (ia + p.shift[a]) * p.dx;
   }
   const double ref = (mode == kFP32) ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
-  const bool half = p.scheme == kHalfWay;
+  const bool half = !wall_full<V>(p);
   const long long ps = p.pstride;
   const int want = side ? -1 : 1;
   double val[q_of(D)];
-  wall_analytic<D, TAN>(p, x, t_n, [&](int k) { return p.cv[k][0] == want; },
-                        [](int) { return 0; }, val);
+  wall_analytic<D, TAN, V>(p, x, t_n, [&](int k) { return p.cv[k][0] == want; },
+                           [](int) { return 0; }, val);
   static_for<0, q_of(D)>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int cx = vel_comp(D, k, 0);
@@ -1150,7 +1169,7 @@ __device__ __forceinline__ int wall_row(const KParams& p, int idx) {
   return row;
 }
 
-template <int D, class T, bool TAN>
+template <int D, class T, bool TAN, int V>
 __global__ void __launch_bounds__(256)
     k_wall(const T* __restrict__ src, T* __restrict__ dst, const KParams p, const double t_n) {
   constexpr int Q = q_of(D);
@@ -1171,14 +1190,14 @@ __global__ void __launch_bounds__(256)
       constexpr int k = decltype(K)::value;
       f[k] = src[k * ps + node + pull_offset<D, k>(r)];
     });
-    wall_values<D, TAN, T>(f, p, r, t_n, ref, [&](int kb) {
+    wall_values<D, TAN, V, T>(f, p, r, t_n, ref, [&](int kb) {
       return static_cast<double>(src[kb * ps + node]) + p.omega[kb] * ref;
     });
     collide_store<D, T>(f, dst, ps, node, p);
   }
 }
 
-template <int D, bool TAN>
+template <int D, bool TAN, int V>
 __global__ void __launch_bounds__(256)
     k_wall_split(const float* __restrict__ gsrc, float* __restrict__ gdst,
                  const double* __restrict__ phisrc, double* __restrict__ phidst, const KParams p,
@@ -1195,7 +1214,7 @@ __global__ void __launch_bounds__(256)
     const int node = r.rowbase + x;
     double f[Q];
     split_pull<D>(f, gsrc, phisrc, ps, node, r, p);
-    wall_values<D, TAN, double>(f, p, r, t_n, 0.0, [&](int kb) {
+    wall_values<D, TAN, V, double>(f, p, r, t_n, 0.0, [&](int kb) {
       return split_fstar<D>(gsrc, phisrc, ps, node, kb, p);
     });
     split_store<D>(f, gdst, phidst, ps, node, p);
@@ -1435,6 +1454,61 @@ static unsigned grid_for(long long nodes, int threads) {
   return static_cast<unsigned>(b);
 }
 
+// Per-variant launches of the wall kernels (d = 2 and 3; d = 1 and 4 take the
+// run-time variant).
+template <int D, class T, bool TAN>
+static void launch_xface(unsigned blocks, hipStream_t stream, T* buf, const KParams& p, double t,
+                         int mode) {
+  const dim3 g(blocks), b(256);
+  if constexpr (D == 1 || D == 4) {
+    hipLaunchKernelGGL((k_xface<D, T, TAN, -1>), g, b, 0, stream, buf, p, t, mode);
+  } else {
+    switch (wall_variant(p)) {
+      case 0: hipLaunchKernelGGL((k_xface<D, T, TAN, 0>), g, b, 0, stream, buf, p, t, mode); break;
+      case 1: hipLaunchKernelGGL((k_xface<D, T, TAN, 1>), g, b, 0, stream, buf, p, t, mode); break;
+      case 2: hipLaunchKernelGGL((k_xface<D, T, TAN, 2>), g, b, 0, stream, buf, p, t, mode); break;
+      default: hipLaunchKernelGGL((k_xface<D, T, TAN, 3>), g, b, 0, stream, buf, p, t, mode);
+    }
+  }
+}
+
+template <int D, class T, bool TAN>
+static void launch_wall(dim3 g, dim3 b, hipStream_t stream, const T* src, T* dst, const KParams& p,
+                        double t) {
+  if constexpr (D == 1 || D == 4) {
+    hipLaunchKernelGGL((k_wall<D, T, TAN, -1>), g, b, 0, stream, src, dst, p, t);
+  } else {
+    switch (wall_variant(p)) {
+      case 0: hipLaunchKernelGGL((k_wall<D, T, TAN, 0>), g, b, 0, stream, src, dst, p, t); break;
+      case 1: hipLaunchKernelGGL((k_wall<D, T, TAN, 1>), g, b, 0, stream, src, dst, p, t); break;
+      case 2: hipLaunchKernelGGL((k_wall<D, T, TAN, 2>), g, b, 0, stream, src, dst, p, t); break;
+      default: hipLaunchKernelGGL((k_wall<D, T, TAN, 3>), g, b, 0, stream, src, dst, p, t);
+    }
+  }
+}
+
+template <int D, bool TAN>
+static void launch_wall_split(dim3 g, dim3 b, hipStream_t stream, const float* gs, float* gd,
+                              const double* ps, double* pd, const KParams& p, double t) {
+  if constexpr (D == 1 || D == 4) {
+    hipLaunchKernelGGL((k_wall_split<D, TAN, -1>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+  } else {
+    switch (wall_variant(p)) {
+      case 0:
+        hipLaunchKernelGGL((k_wall_split<D, TAN, 0>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+        break;
+      case 1:
+        hipLaunchKernelGGL((k_wall_split<D, TAN, 1>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_wall_split<D, TAN, 2>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+        break;
+      default:
+        hipLaunchKernelGGL((k_wall_split<D, TAN, 3>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+    }
+  }
+}
+
 template <int D, bool TAN>
 static hipError_t step_dt(const KParams& p, int mode, const void* src, void* dst,
                           const double* phi_src, double* phi_dst, long long n,
@@ -1449,11 +1523,11 @@ static hipError_t step_dt(const KParams& p, int mode, const void* src, void* dst
   if (p.bc[0] != 0) {
     const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
     if (mode == kFP64)
-      hipLaunchKernelGGL((k_xface<D, double, TAN>), dim3(xb), dim3(256), 0, stream,
-                         static_cast<double*>(const_cast<void*>(src)), p, t_n, mode);
+      launch_xface<D, double, TAN>(xb, stream, static_cast<double*>(const_cast<void*>(src)), p,
+                                   t_n, mode);
     else
-      hipLaunchKernelGGL((k_xface<D, float, TAN>), dim3(xb), dim3(256), 0, stream,
-                         static_cast<float*>(const_cast<void*>(src)), p, t_n, mode);
+      launch_xface<D, float, TAN>(xb, stream, static_cast<float*>(const_cast<void*>(src)), p,
+                                  t_n, mode);
   }
   mark(0);
   if (mode == kFP64) {
@@ -1462,22 +1536,21 @@ static hipError_t step_dt(const KParams& p, int mode, const void* src, void* dst
     hipLaunchKernelGGL((k_step<D, double>), grid, block, 0, stream, a, b, p);
     mark(1);
     if (p.wall_rows > 0)
-      hipLaunchKernelGGL((k_wall<D, double, TAN>), wgrid, block, 0, stream, a, b, p, t_n);
+      launch_wall<D, double, TAN>(wgrid, block, stream, a, b, p, t_n);
   } else if (mode == kFP32) {
     auto* a = static_cast<const float*>(src);
     auto* b = static_cast<float*>(dst);
     hipLaunchKernelGGL((k_step<D, float>), grid, block, 0, stream, a, b, p);
     mark(1);
     if (p.wall_rows > 0)
-      hipLaunchKernelGGL((k_wall<D, float, TAN>), wgrid, block, 0, stream, a, b, p, t_n);
+      launch_wall<D, float, TAN>(wgrid, block, stream, a, b, p, t_n);
   } else {
     auto* a = static_cast<const float*>(src);
     auto* b = static_cast<float*>(dst);
     hipLaunchKernelGGL((k_step_split<D>), grid, block, 0, stream, a, b, phi_src, phi_dst, p);
     mark(1);
     if (p.wall_rows > 0)
-      hipLaunchKernelGGL((k_wall_split<D, TAN>), wgrid, block, 0, stream, a, b, phi_src, phi_dst,
-                         p, t_n);
+      launch_wall_split<D, TAN>(wgrid, block, stream, a, b, phi_src, phi_dst, p, t_n);
   }
   mark(2);
   return hipGetLastError();
@@ -1517,12 +1590,11 @@ static hipError_t fused_pair_t(const KParams& p, const T* A, T* B, T* C, long lo
   };
   if (p.bc[0] != 0) {
     const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
-    hipLaunchKernelGGL((k_xface<3, T, TAN>), dim3(xb), dim3(256), 0, stream, const_cast<T*>(A),
-                       p, t0, mode);
-    hipLaunchKernelGGL((k_xface<3, T, TAN>), dim3(xb), dim3(256), 0, stream, B, p, t1, mode);
+    launch_xface<3, T, TAN>(xb, stream, const_cast<T*>(A), p, t0, mode);
+    launch_xface<3, T, TAN>(xb, stream, B, p, t1, mode);
   }
   if (p.wall_rows > 0)
-    hipLaunchKernelGGL((k_wall<3, T, TAN>), wgrid, block, 0, stream, A, C, p, t0);
+    launch_wall<3, T, TAN>(wgrid, block, stream, A, C, p, t0);
   const int tiles_xy = ((p.n[0] + S::TX - 1) / S::TX) * ((p.n[1] + S::TY - 1) / S::TY);
   const int zc = fuse_zchunk(tiles_xy, p.n[2]);
   const dim3 grid(static_cast<unsigned>(tiles_xy * ((p.n[2] + zc - 1) / zc)));
@@ -1530,7 +1602,7 @@ static hipError_t fused_pair_t(const KParams& p, const T* A, T* B, T* C, long lo
   hipLaunchKernelGGL((k_fused2<T, HALF>), grid, dim3(S::NT), lds, stream, A, B, C, p, zc);
   mark(1);
   if (p.wall_rows > 0)
-    hipLaunchKernelGGL((k_wall<3, T, TAN>), wgrid, block, 0, stream, C, B, p, t1);
+    launch_wall<3, T, TAN>(wgrid, block, stream, C, B, p, t1);
   mark(2);
   return hipGetLastError();
 }
@@ -1567,14 +1639,12 @@ static hipError_t fused_pair_split(const KParams& p, const FusedBufs& fb, long l
     KParams p2 = p;
     p2.xdata = fb.xdata2;
     const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
-    hipLaunchKernelGGL((k_xface<3, float, TAN>), dim3(xb), dim3(256), 0, stream,
-                       const_cast<float*>(gA), p, t0, static_cast<int>(kSplit));
-    hipLaunchKernelGGL((k_xface<3, float, TAN>), dim3(xb), dim3(256), 0, stream, gB, p2, t1,
-                       static_cast<int>(kSplit));
+    launch_xface<3, float, TAN>(xb, stream, const_cast<float*>(gA), p, t0,
+                                static_cast<int>(kSplit));
+    launch_xface<3, float, TAN>(xb, stream, gB, p2, t1, static_cast<int>(kSplit));
   }
   if (p.wall_rows > 0)
-    hipLaunchKernelGGL((k_wall_split<3, TAN>), wgrid, block, 0, stream, gA, gC, fb.phiA, fb.phiC,
-                       p, t0);
+    launch_wall_split<3, TAN>(wgrid, block, stream, gA, gC, fb.phiA, fb.phiC, p, t0);
   const int tiles_xy = ((p.n[0] + S::TX - 1) / S::TX) * ((p.n[1] + S::TY - 1) / S::TY);
   const int zc = fuse_zchunk(tiles_xy, p.n[2]);
   const dim3 grid(static_cast<unsigned>(tiles_xy * ((p.n[2] + zc - 1) / zc)));
@@ -1583,8 +1653,7 @@ static hipError_t fused_pair_split(const KParams& p, const FusedBufs& fb, long l
                      fb.phiB, fb.phiC, p, static_cast<const double*>(fb.xdata2), zc);
   mark(1);
   if (p.wall_rows > 0)
-    hipLaunchKernelGGL((k_wall_split<3, TAN>), wgrid, block, 0, stream, gC, gB, fb.phiC, fb.phiB,
-                       p, t1);
+    launch_wall_split<3, TAN>(wgrid, block, stream, gC, gB, fb.phiC, fb.phiB, p, t1);
   mark(2);
   return hipGetLastError();
 }
@@ -1627,12 +1696,11 @@ static hipError_t fused_pair2_t(const KParams& p, const T* A, T* B, T* C, long l
   };
   if (p.bc[0] != 0) {
     const unsigned xb = static_cast<unsigned>((2 * p.rows + 255) / 256);
-    hipLaunchKernelGGL((k_xface<2, T, TAN>), dim3(xb), dim3(256), 0, stream, const_cast<T*>(A),
-                       p, t0, mode);
-    hipLaunchKernelGGL((k_xface<2, T, TAN>), dim3(xb), dim3(256), 0, stream, B, p, t1, mode);
+    launch_xface<2, T, TAN>(xb, stream, const_cast<T*>(A), p, t0, mode);
+    launch_xface<2, T, TAN>(xb, stream, B, p, t1, mode);
   }
   if (p.wall_rows > 0)
-    hipLaunchKernelGGL((k_wall<2, T, TAN>), wgrid, block, 0, stream, A, C, p, t0);
+    launch_wall<2, T, TAN>(wgrid, block, stream, A, C, p, t0);
   const int tiles_x = (p.n[0] + S::TX - 1) / S::TX;
   const int yc = fuse_ychunk(tiles_x, p.n[1]);
   const dim3 grid(static_cast<unsigned>(tiles_x * ((p.n[1] + yc - 1) / yc)));
@@ -1640,7 +1708,7 @@ static hipError_t fused_pair2_t(const KParams& p, const T* A, T* B, T* C, long l
   hipLaunchKernelGGL((k_fused2_d2<T, HALF>), grid, dim3(S::NT), lds, stream, A, B, C, p, yc);
   mark(1);
   if (p.wall_rows > 0)
-    hipLaunchKernelGGL((k_wall<2, T, TAN>), wgrid, block, 0, stream, C, B, p, t1);
+    launch_wall<2, T, TAN>(wgrid, block, stream, C, B, p, t1);
   mark(2);
   return hipGetLastError();
 }
