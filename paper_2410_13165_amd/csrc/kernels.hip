@@ -516,9 +516,11 @@ __device__ __forceinline__ void collide_vals(T (&f)[q_of(D)], const KParams& p) 
 #pragma unroll
     for (int k = 0; k < Q; ++k) phi += f[k];
     const double oms = 1.0 - p.s;
-    const double dtR = p.dt * p.R;
+    // omega_k (s phi + dt R) + (1 - s) f_k: one uniform constant per
+    // population (omega_k) instead of two (s omega_k, dt R omega_k)
+    const double a = fma(p.s, phi, p.dt * p.R);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) f[k] = fma(p.s * p.omega[k], phi, fma(oms, f[k], dtR * p.omega[k]));
+    for (int k = 0; k < Q; ++k) f[k] = fma(p.omega[k], a, oms * f[k]);
   }
 }
 
@@ -904,19 +906,23 @@ __global__ void __launch_bounds__(256)
 }
 
 // Split representation: phi (float64) and g_k = f_k - omega_k phi (float32),
-// pre-collision.  f*_k(y) = omega_k phi(y) + (1 - s) g_k(y) + dt omega_k R, so
-// the pull needs phi and g_k at the upwind node only; arithmetic is float64.
+// pre-collision.  f*_k(y) = omega_k (phi(y) + dt R) + (1 - s) g_k(y), so the
+// pull needs phi and g_k at the upwind node only; arithmetic is float64.
+// Every kernel of the mode evaluates f* with split_fstar_val (two-step passes
+// equal single steps bit for bit), with one uniform constant per population.
+__device__ __forceinline__ double split_fstar_val(double omega, double phi, float g,
+                                                  const KParams& p) {
+  return fma(omega, phi + p.dt * p.R, (1.0 - p.s) * static_cast<double>(g));
+}
+
 template <int D>
 __device__ __forceinline__ void split_pull(double (&f)[q_of(D)], const float* __restrict__ gsrc,
                                            const double* __restrict__ phisrc, long long ps,
                                            int node, const RowInfo<D>& r, const KParams& p) {
-  const double oms = 1.0 - p.s;
-  const double dtR = p.dt * p.R;
   static_for<0, q_of(D)>([&](auto K) {
     constexpr int k = decltype(K)::value;
     const int idx = node + pull_offset<D, k>(r);
-    f[k] = fma(p.omega[k], phisrc[idx],
-               fma(oms, static_cast<double>(gsrc[k * ps + idx]), dtR * p.omega[k]));
+    f[k] = split_fstar_val(p.omega[k], phisrc[idx], gsrc[k * ps + idx], p);
   });
 }
 
@@ -924,8 +930,7 @@ template <int D>
 __device__ __forceinline__ double split_fstar(const float* __restrict__ gsrc,
                                               const double* __restrict__ phisrc, long long ps,
                                               int node, int kb, const KParams& p) {
-  return fma(p.omega[kb], phisrc[node],
-             fma(1.0 - p.s, static_cast<double>(gsrc[kb * ps + node]), p.dt * p.R * p.omega[kb]));
+  return split_fstar_val(p.omega[kb], phisrc[node], gsrc[kb * ps + node], p);
 }
 
 template <int D>
@@ -1014,8 +1019,6 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
   const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * zc;
   const int zend = min(zc0 + zc, n2);
   const int iters = zend - zc0 + 2;
-  const double oms = 1.0 - p.s;
-  const double dtR = p.dt * p.R;
   for (int it = 0; it < iters; ++it) {
     const int zp = zc0 - 1 + it;
     // plain region order: with two items per thread the halo-column items of
@@ -1109,7 +1112,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
           const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
           const double ph = lphi[((it - src_it) % 3) * R + rr];
           const float gk = lg[fuse_slot<HALF, k>(it - src_it) * R + rr];
-          f[k] = fma(p.omega[k], ph, fma(oms, static_cast<double>(gk), dtR * p.omega[k]));
+          f[k] = split_fstar_val(p.omega[k], ph, gk, p);
         });
         if (ri.lo[0] || ri.hi[0]) {
           const double* W = xd2 + (ri.hi[0] ? SX * p.rows : 0) + row;
@@ -1124,8 +1127,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
                   constexpr int kb = opp_index(D, k);
                   const double ph = lphi[((it - 1) % 3) * R + own];
                   const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
-                  v -= fma(p.omega[kb], ph,
-                           fma(1.0 - p.s, static_cast<double>(gb), p.dt * p.R * p.omega[kb]));
+                  v -= split_fstar_val(p.omega[kb], ph, gb, p);
                 }
                 f[k] = v;
               }
