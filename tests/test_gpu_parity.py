@@ -239,6 +239,18 @@ def test_example1_source_term_fp32_reference():
     _check_pair(2, (41, 41), 1.0 / 40, spec, 200, bc=["fullway"] * 2, precision="fp32_split")
 
 
+@pytest.mark.parametrize("scheme", ["fullway", "halfway"])
+def test_exponential_field_d3(scheme):
+    """An exponential exact solution in 3D: the d = 3 wall kernels of the
+    exponential variants (full-way and half-way) against the oracle, float64
+    at order 4 and the split mode at order 3."""
+    spec = {"kind": "exp_sum", "amps": [0.7, -0.4], "kvecs": [[-1.0, 0.5, 0.8], [0.6, -0.9, 0.3]],
+            "phases": [0.0, 0.0], "u": [0.06, -0.05, 0.08], "R": 0.5}
+    _check_pair(3, (26, 19, 21), 1.0 / 25, spec, 20, bc=[scheme] * 3)
+    _check_pair(3, (26, 19, 21), 1.0 / 25, spec, 20, bc=[scheme] * 3, P=3,
+                precision="fp32_split")
+
+
 def test_example3_d4q33_halfway_small_u():
     spec = inputs.diagonal_sine(4, [1e-3] * 4)
     _check_pair(4, (10, 10, 10, 10), 0.2, spec, 8, bc=["halfway"] * 4, origin=[-1.0] * 4)
