@@ -67,6 +67,19 @@ struct FuseShape<double, true> {
   static constexpr int TX = 32, TY = 12, NT = 512, SLOTS = 43;
 };
 
+// The forward pass with half-way x_1 walls needs, at an x_1-face node of
+// output plane z - 1, the step-1 value f*_kbar of that node, for every kbar
+// opposite an unknown k.  Of these only kbar = (-+1, 0, -1) has c_3 = -1,
+// whose single plane slot the next plane overwrites, so the pass keeps that
+// one value per face node in a side buffer (two faces x (TY + 2) rows x two
+// plane parities) instead of a second slot for every c_3 = -1 population:
+// its LDS has the full-way slots and tile.  (The split and adjoint passes
+// keep the 43-slot layout of FuseShape<T, true>.)
+template <class T, bool HALF>
+struct FuseFwdShape : FuseShape<T, false> {
+  static constexpr int SIDE = HALF ? 4 * (FuseShape<T, false>::TY + 2) : 0;
+};
+
 // index of population k among those with the same c_3
 constexpr int cz_index(int k) {
   const int cz = vel_comp(3, k, 2);

@@ -604,14 +604,15 @@ __global__ void __launch_bounds__(256)
 // both before the launch).  Every node goes through exactly the arithmetic of
 // k_step, so the result is bitwise that of two single steps.
 template <class T, bool HALF>
-__global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
+__global__ void __launch_bounds__((FuseFwdShape<T, HALF>::NT))
     k_fused2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p,
              const int zc) {
-  using S = FuseShape<T, HALF>;
+  using S = FuseFwdShape<T, HALF>;
   constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
   constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
   extern __shared__ __align__(16) unsigned char fuse_lds[];
   T* lds = reinterpret_cast<T*>(fuse_lds);
+  T* side = lds + S::SLOTS * R;  // half-way only: side[((parity * 2) + face) * RY + ry]
   const long long ps = p.pstride;
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
   int tx_, ty_, tz_;
@@ -682,8 +683,21 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
       }
       static_for<0, Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
-        lds[fuse_slot<HALF, k>(it) * R + r] = f[k];
+        lds[fuse_slot<false, k>(it) * R + r] = f[k];
       });
+      if (HALF && (ri.lo[0] || ri.hi[0])) {
+        // f*_kbar with c_3(kbar) = -1 opposite the face's unknowns, for step 2
+        // of this plane (read one iteration later)
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr int cx = vel_comp(D, k, 0);
+          if constexpr (cx != 0 && vel_comp(D, k, 2) == 1) {
+            const int face = cx == 1 ? 0 : 1;
+            if ((cx == 1) ? ri.lo[0] : ri.hi[0])
+              side[((it & 1) * 2 + face) * RY + ry] = f[opp_index(D, k)];
+          }
+        });
+      }
     }
     __syncthreads();
     // ---- step 2 on output plane zp - 1
@@ -708,7 +722,7 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
           constexpr Vec4i c = vel_vec(D, k);
           constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
           const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
-          f[k] = lds[fuse_slot<HALF, k>(it - src_it) * R + rr];
+          f[k] = lds[fuse_slot<false, k>(it - src_it) * R + rr];
         });
         if (ri.lo[0] || ri.hi[0]) {
           static_for<0, Q>([&](auto K) {
@@ -726,8 +740,12 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
             constexpr int cx = vel_comp(D, k, 0);
             if constexpr (cx != 0) {
               constexpr int kb = opp_index(D, k);
-              if ((cx == 1) ? ri.lo[0] : ri.hi[0])
-                f[k] -= lds[fuse_slot<HALF, kb>(it - 1) * R + own];
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                if constexpr (vel_comp(D, k, 2) == 1)
+                  f[k] -= side[(((it - 1) & 1) * 2 + (cx == 1 ? 0 : 1)) * RY + oy + 1];
+                else
+                  f[k] -= lds[fuse_slot<false, kb>(it - 1) * R + own];
+              }
             }
           });
         }
@@ -1570,9 +1588,9 @@ static hipError_t step_d(const KParams& p, int mode, const void* src, void* dst,
 template <class T, bool TAN, bool HALF>
 static hipError_t fused_pair_t(const KParams& p, const T* A, T* B, T* C, long long n,
                                hipStream_t stream, hipEvent_t* ev) {
-  using S = FuseShape<T, HALF>;
+  using S = FuseFwdShape<T, HALF>;
   constexpr int R = (S::TX + 2) * (S::TY + 2);
-  constexpr size_t lds = sizeof(T) * S::SLOTS * R;
+  constexpr size_t lds = sizeof(T) * (S::SLOTS * R + S::SIDE);
   static_assert(lds <= 160 * 1024, "fused tile exceeds the LDS of a CU");
   constexpr int mode = std::is_same<T, float>::value ? kFP32 : kFP64;
   static bool attr_set = false;
