@@ -41,7 +41,8 @@ METRIC = "D3Q19 MLUPS & % HBM peak, FP32 vs FP64 at fixed L2 error; adjoint/fwd 
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_fused2_d3q19_512_fp32_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_13165_amd", "csrc", f)
-                  for f in ("kernels.hip", "fuse.hpp", "engine.hpp", "lattice.hpp")]
+                  for f in ("kernels.hip", "kernels.hpp", "fuse.hpp", "engine.hpp",
+                            "lattice.hpp")]
 
 
 def kernel_source_hash() -> str:

@@ -5,12 +5,14 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "stability.hip", "capi.hip"]
+SOURCES = ["kernels.hip", "walls_d2.hip", "walls_d3.hip", "walls_d3t.hip", "walls_d14.hip",
+           "adjoint.hip", "stability.hip", "capi.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -21,25 +23,51 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def command(out: str = LIB) -> list[str]:
-    return [
-        hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-        # packed fp32 instructions stay off: only scalar/float2 code is emitted
-        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-I", os.path.join(ROOT, "include"),
-        "-o", out,
-    ] + [os.path.join(CSRC, s) for s in SOURCES]
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # packed fp32 instructions stay off: only scalar/float2 code is emitted
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(ROOT, "include"),
+]
+
+
+def compile_command(src: str, obj: str) -> list[str]:
+    return [hipcc()] + FLAGS + ["-c", "-o", obj, os.path.join(CSRC, src)]
+
+
+def link_command(objs: list[str], out: str = LIB) -> list[str]:
+    return [hipcc(), f"--offload-arch={ARCH}", "-fPIC", "-shared", "-o", out] + objs
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel (each translation unit
+    carries its own gfx950 code object), then link liblbm.so."""
     tmp = LIB + ".tmp"
-    cmd = command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building liblbm.so")
+    with tempfile.TemporaryDirectory(prefix="lbm_build_") as work:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(work, os.path.splitext(src)[0] + ".o")
+            cmd = compile_command(src, obj)
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                stderr=subprocess.STDOUT, text=True)))
+            objs.append(obj)
+        failed = []
+        for src, proc in procs:
+            out, _ = proc.communicate()
+            if proc.returncode != 0:
+                sys.stderr.write(out)
+                failed.append(src)
+        if failed:
+            raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
+        cmd = link_command(objs, tmp)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking liblbm.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,0 +1,1419 @@
+// Device code of the stream-collide, wall, initialisation and reduction
+// kernels (templates), shared by kernels.hip (bulk passes and launchers) and
+// walls_d*.hip (the wall-row and x_1-face kernels).  A kernel template is compiled
+// only in the translation unit that launches it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "engine.hpp"
+#include "fuse.hpp"
+
+namespace lbm {
+
+// ----------------------------------------------------------------- helpers --
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+struct Vec4i {
+  int v[4];
+};
+
+constexpr Vec4i vel_vec(int D, int k) {
+  Vec4i r{{0, 0, 0, 0}};
+  for (int a = 0; a < D; ++a) r.v[a] = vel_comp(D, k, a);
+  return r;
+}
+
+template <int D>
+struct RowInfo {
+  int i[D];
+  int dm[D];     // node offset of the upwind neighbour for c_a = +1 (wrapped)
+  int dp[D];     // node offset of the upwind neighbour for c_a = -1 (wrapped)
+  bool lo[D];    // node lies on the lower Dirichlet wall of axis a
+  bool hi[D];    // node lies on the upper Dirichlet wall of axis a
+  bool rowwall;  // some axis a >= 1 puts the whole row on a wall
+  int rowbase;
+};
+
+template <int D>
+__device__ __forceinline__ void row_setup(const KParams& p, int row, RowInfo<D>& r) {
+  int rr = row;
+  r.rowwall = false;
+#pragma unroll
+  for (int a = 1; a < D; ++a) {
+    const int n = p.n[a];
+    const int ia = rr % n;
+    rr /= n;
+    const int st = p.stride[a];
+    r.i[a] = ia;
+    r.dm[a] = (ia == 0) ? (n - 1) * st : -st;
+    r.dp[a] = (ia == n - 1) ? -(n - 1) * st : st;
+    const bool wall = p.bc[a] != 0;
+    r.lo[a] = wall && ia == 0;
+    r.hi[a] = wall && ia == n - 1;
+    r.rowwall = r.rowwall || r.lo[a] || r.hi[a];
+  }
+  r.rowbase = row * p.n[0];
+}
+
+// row_setup for d = 3 from the row's coordinates (i_2, i_3), without the
+// divisions that recover them from the row index
+__device__ __forceinline__ void row_setup_yz(const KParams& p, int iy, int iz, RowInfo<3>& r) {
+  const int ia[3] = {0, iy, iz};
+  r.rowwall = false;
+#pragma unroll
+  for (int a = 1; a < 3; ++a) {
+    const int n = p.n[a];
+    const int st = p.stride[a];
+    r.i[a] = ia[a];
+    r.dm[a] = (ia[a] == 0) ? (n - 1) * st : -st;
+    r.dp[a] = (ia[a] == n - 1) ? -(n - 1) * st : st;
+    const bool wall = p.bc[a] != 0;
+    r.lo[a] = wall && ia[a] == 0;
+    r.hi[a] = wall && ia[a] == n - 1;
+    r.rowwall = r.rowwall || r.lo[a] || r.hi[a];
+  }
+  r.rowbase = (iz * p.n[1] + iy) * p.n[0];
+}
+
+template <int D>
+__device__ __forceinline__ void col_setup(const KParams& p, int x, RowInfo<D>& r) {
+  const int n0 = p.n[0];
+  r.i[0] = x;
+  r.dm[0] = (x == 0) ? n0 - 1 : -1;
+  r.dp[0] = (x == n0 - 1) ? -(n0 - 1) : 1;
+  const bool wall = p.bc[0] != 0;
+  r.lo[0] = wall && x == 0;
+  r.hi[0] = wall && x == n0 - 1;
+}
+
+template <int D, int k>
+__device__ __forceinline__ int pull_offset(const RowInfo<D>& r) {
+  constexpr Vec4i c = vel_vec(D, k);
+  int off = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (c.v[a] == 1) off += r.dm[a];
+    if (c.v[a] == -1) off += r.dp[a];
+  }
+  return off;
+}
+
+template <int D, int k>
+__device__ __forceinline__ bool outside(const RowInfo<D>& r) {
+  constexpr Vec4i c = vel_vec(D, k);
+  bool o = false;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (c.v[a] == 1) o = o || r.lo[a];
+    if (c.v[a] == -1) o = o || r.hi[a];
+  }
+  return o;
+}
+
+// Lowest axis through whose wall population k enters the node from outside
+// (0 when it enters through none).
+template <int D, int k>
+__device__ __forceinline__ int wall_axis(const RowInfo<D>& r) {
+  constexpr Vec4i c = vel_vec(D, k);
+  int ax = -1;
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a) {
+    if ((c.v[a] == 1 && r.lo[a]) || (c.v[a] == -1 && r.hi[a])) ax = a;
+  }
+  return ax < 0 ? 0 : ax;
+}
+
+template <int D>
+__device__ __forceinline__ bool on_wall(const RowInfo<D>& r) {
+  return r.rowwall || r.lo[0] || r.hi[0];
+}
+
+// Error-free sum a + b = s + e (Knuth's TwoSum), used for the compensated
+// float32 moment sums.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+// -------------------------------------------------- analytic field values ---
+
+// phi*(x, t) for the RMSE reference and the analytic initial state.
+template <int D>
+__device__ double field_value(const FieldDev& F, const KParams& p, const double (&x)[D],
+                              double t) {
+  double v = 0.0;
+  if (F.kind == kFieldTanh) {
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double y = x[a] - p.u[a] * t - F.center[a];
+      r2 += y * y;
+    }
+    v = 0.5 - 0.5 * tanh((F.Rr - sqrt(r2)) / (2.0 * F.W));
+  } else {
+    for (int j = 0; j < F.nmodes; ++j) {
+      double ph = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) ph += F.kvec[j][a] * (x[a] - p.u[a] * t);
+      v += (F.kind == kFieldCos) ? F.amp[j] * cos(ph + F.phase[j]) : F.amp[j] * exp(ph);
+    }
+  }
+  return v + p.R * t;
+}
+
+// phi*(x, 0) and its gradient.
+template <int D>
+__device__ void field_initial(const FieldDev& F, const KParams& p, const double (&x)[D],
+                              double& phi, double (&grad)[D]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) grad[a] = 0.0;
+  phi = 0.0;
+  if (F.kind == kFieldTanh) {
+    double y[D];
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      y[a] = x[a] - F.center[a];
+      r2 += y[a] * y[a];
+    }
+    const double r = sqrt(r2);
+    const double z = (F.Rr - r) / (2.0 * F.W);
+    phi = 0.5 - 0.5 * tanh(z);
+    const double ch = cosh(z);
+    const double dphi_dr = 0.5 / (ch * ch) / (2.0 * F.W);
+    if (r > 0.0) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) grad[a] = dphi_dr * y[a] / r;
+    }
+    return;
+  }
+  for (int j = 0; j < F.nmodes; ++j) {
+    double ph = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ph += F.kvec[j][a] * x[a];
+    if (F.kind == kFieldCos) {
+      double s, c;
+      sincos(ph + F.phase[j], &s, &c);
+      phi += F.amp[j] * c;
+#pragma unroll
+      for (int a = 0; a < D; ++a) grad[a] -= F.amp[j] * F.kvec[j][a] * s;
+    } else {
+      const double e = F.amp[j] * exp(ph);
+      phi += e;
+#pragma unroll
+      for (int a = 0; a < D; ++a) grad[a] += F.kvec[j][a] * e;
+    }
+  }
+}
+
+// --------------------------------------------------------- wall schemes -----
+//
+// The exact solution is phi*(x,t) = F(x - u t) + R t, so on one Fourier or
+// exponential mode every time derivative multiplies by w = -kappa.u and every
+// derivative along c_k by pc = kappa.c_k; derivatives of cos cycle through
+// cos, -sin, -cos, sin.
+//
+// Full-way, eq. (bun-1) at (x_b = node, t_{n+1}): with a = dt d_t and
+// b = dt c_k.grad the printed polynomial is 1 - (a+b)/2 + (a+b)^3/24 applied to
+// f^eq (its R terms cancel against the R t part), i.e. per mode
+//   omega_k [F - (dt/2) v.grad F + (dt^3/24) (v.grad)^3 F] + omega_k R t,
+// v = c_k - u; order 3 drops the cubic term, order 1 keeps F only.
+//
+// Half-way, eq. (bun2) at (x_b = x_f - c_k dx/2, t_n): the sum of
+//   (omega_k + omega_kbar) [1 + (dt/2) d_t - (dt^2/8)(c.grad)^2
+//                           - (dt^3/16)(c.grad)^2 d_t - (dt^3/24) d_t^3]
+//   (omega_k - omega_kbar) [-(dt^2/4) c.grad d_t - (dt^3/8) c.grad d_t^2]
+// applied to phi*, plus (dt/2)(R_k + R_kbar), truncated at order P; the new
+// population is that minus the post-collision f*_kbar at x_f.
+
+// The wall kernels of d = 2 and 3 are compiled per variant of the wall
+// formula, V = full-way (bit 0) | cosine field (bit 1; otherwise exponential):
+// a kernel then holds the registers of one variant, not of all four (which
+// left one wavefront per SIMD).  V = -1 takes both from the lattice at run
+// time (d = 1 and 4, to bound the build).
+template <int V>
+__device__ __forceinline__ bool wall_full(const KParams& p) {
+  if constexpr (V < 0) return p.scheme == kFullWay;
+  else return (V & 1) != 0;
+}
+template <int V>
+__device__ __forceinline__ bool wall_cos(const KParams& p) {
+  if constexpr (V < 0) return p.field.kind == kFieldCos;
+  else return (V & 2) != 0;
+}
+inline int wall_variant(const KParams& p) {
+  return (p.scheme == kFullWay ? 1 : 0) | (p.field.kind == kFieldCos ? 2 : 0);
+}
+
+// Analytic wall values at one node (coordinates x) for the step
+// t_n -> t_{n+1}, for every population k with sel(k) true, into val[k]:
+// full-way: eq. (bun-1) at (x, t_{n+1}), the whole pre-collision f_k;
+// half-way: the right side of eq. (bun2) at (x - c_k dx/2, t_n), to which the
+// caller adds -f*_kbar(x, t_n).  One sincos (or exp) per mode serves every
+// population: the half-way shift -(dx/2) kappa . c_k is applied by rotating
+// with the per-axis factors of FieldDev::rot.
+//
+// Every derivative of a mode along c_k multiplies it by kappa . c_k.  With
+// tangential wall data (TAN, p.wall_data == 1) that factor is assembled from what
+// the data on the wall of axis j = axis(k) provide, as Remark 1 does with the
+// equation: c_k . grad F = alpha . grad_tan F + beta d_t F with
+// alpha = c_k - (c_kj / u_j) u (tangential, alpha_j = 0) and beta = -c_kj / u_j,
+// i.e. the factor alpha . kappa + beta (-kappa . u).
+template <int D, bool TAN, int V, class Sel, class Axis>
+__device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x)[kMaxDim],
+                                              double t_n, Sel sel, Axis axis,
+                                              double (&val)[q_of(D)]) {
+  constexpr int Q = q_of(D);
+  const FieldDev& F = p.field;
+  const double dt = p.dt;
+  const bool full = wall_full<V>(p);
+  const bool is_cos = wall_cos<V>(p);
+  const double o2 = p.P >= 2 ? 1.0 : 0.0;
+  const double o3 = p.P >= 3 ? 1.0 : 0.0;
+  const double o4 = p.P >= 4 ? 1.0 : 0.0;
+  const double dt2 = dt * dt, dt3 = dt2 * dt;
+  const double t = full ? t_n + dt : t_n;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) val[k] = 0.0;
+#pragma unroll 1
+  for (int j = 0; j < F.nmodes; ++j) {
+    double ph = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ph += F.kvec[j][a] * (x[a] - p.u[a] * t);
+    double C = 0.0, S = 0.0, E = 0.0;
+    if (is_cos)
+      sincos(ph + F.phase[j], &S, &C);
+    else
+      E = exp(ph);
+    const double amp = F.amp[j];
+    const double w = -F.ku[j];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr Vec4i c = vel_vec(D, k);
+      if (!sel(k)) return;
+      double pc = 0.0;
+      if constexpr (!TAN) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) pc += c.v[a] * F.kvec[j][a];
+      } else {
+        const int ja = axis(k);
+        double r = 0.0;  // c_kj / u_j
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          if (a == ja) r = c.v[a] * p.inv_u[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          if (a != ja) pc += (c.v[a] - r * p.u[a]) * F.kvec[j][a];
+        pc -= r * w;
+      }
+      if (full) {
+        const double pv = pc + w;  // kappa . (c_k - u)
+        const double pv3 = pv * pv * pv;
+        if (is_cos)
+          val[k] += amp * (C + (o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3) * S);
+        else
+          val[k] += amp * E * (1.0 - o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3);
+      } else {
+        constexpr int kb = opp_index(D, k);
+        const double wp = p.omega[k] + p.omega[kb];
+        const double wm = p.omega[k] - p.omega[kb];
+        const double T0 = wp;
+        const double T1 = o2 * wp * 0.5 * dt * w;
+        const double T2 = -o3 * (wp * dt2 / 8.0 * pc * pc + wm * dt2 / 4.0 * pc * w);
+        const double T3 = -o4 * (wp * (dt3 / 16.0 * pc * pc * w + dt3 / 24.0 * w * w * w) +
+                                 wm * dt3 / 8.0 * pc * w * w);
+        if (is_cos) {
+          double Ck = C, Sk = S;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (c.v[a] == 0) continue;
+            const double cr = F.rot[j][a][0];
+            const double sr = c.v[a] * F.rot[j][a][1];
+            const double nc = Ck * cr + Sk * sr;
+            Sk = Sk * cr - Ck * sr;
+            Ck = nc;
+          }
+          val[k] += amp * ((T0 - T2) * Ck + (T3 - T1) * Sk);
+        } else {
+          double Ek = E;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (c.v[a] == 1) Ek *= F.rot[j][a][0];
+            if (c.v[a] == -1) Ek *= F.rot[j][a][1];
+          }
+          val[k] += amp * (T0 + T1 + T2 + T3) * Ek;
+        }
+      }
+    });
+  }
+  static_for<0, Q>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    if (!sel(k)) return;
+    if (full) {
+      val[k] = p.omega[k] * (val[k] + p.R * t);
+    } else {
+      constexpr int kb = opp_index(D, k);
+      const double wp = p.omega[k] + p.omega[kb];
+      val[k] += wp * p.R * t_n + o2 * wp * p.R * dt;
+    }
+  });
+}
+
+// Slot of population k among those entering through the lower (c_k1 = +1) or
+// upper (c_k1 = -1) x_1 face; there are 2D - 1 of each.
+constexpr int xface_slot(int D, int k) {
+  const int cx = vel_comp(D, k, 0);
+  int slot = 0;
+  for (int m = 0; m < k; ++m)
+    if (vel_comp(D, m, 0) == cx) ++slot;
+  return slot;
+}
+
+// Wall values of every wall node of a row (any Dirichlet axis; used for the
+// rows that lie on a wall of an axis >= 2 and by the x_1 faces through
+// k_xface).  fstar_local(kb) returns the absolute post-collision f*_kb at the
+// node.
+template <int D, bool TAN, int V, class A, class FStarLocal>
+__device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, const RowInfo<D>& r,
+                                            double t_n, double ref, FStarLocal fstar_local) {
+  double x[kMaxDim] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = p.origin[a] + (r.i[a] + p.shift[a]) * p.dx;
+  bool out[q_of(D)];
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    out[k] = outside<D, k>(r);
+  });
+  int ax[q_of(D)];
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    ax[k] = TAN ? wall_axis<D, k>(r) : 0;
+  });
+  double val[q_of(D)];
+  wall_analytic<D, TAN, V>(p, x, t_n, [&](int k) { return out[k]; },
+                           [&](int k) { return ax[k]; }, val);
+  const bool half = !wall_full<V>(p);
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    if (!out[k]) return;
+    double v = val[k];
+    if (half) v -= fstar_local(opp_index(D, k));
+    f[k] = static_cast<A>(v - p.omega[k] * ref);
+  });
+}
+
+// Analytic wall data of the x_1 faces for the step t_n -> t_{n+1}: one
+// thread per (face, row).  A population with c_k1 = +1 (-1) is unknown on the
+// lower (upper) x_1 face only, so its value for row `row` is kept in its own
+// population plane of the source buffer, at element p.xoff + row past the
+// nodes; the bulk kernel then reads it with the same base address as its
+// pulls.  Values are stored in the storage type T:
+//   full-way  f_k - omega_k ref,
+//   half-way  B_k - (omega_k + omega_kbar) ref  (the bulk kernel subtracts the
+//             stored post-collision kbar value of the node),
+// with ref = phi_ref + R t_{n+1} in float32 mode and 0 otherwise.  The split
+// mode keeps float64 values in p.xdata[(side * (2D-1) + slot) * rows + row].
+template <int D, class T, bool TAN, int V>
+__global__ void __launch_bounds__(256)
+    k_xface(T* __restrict__ buf, const KParams p, const double t_n, const int mode) {
+  constexpr int S = 2 * D - 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * p.rows) return;
+  const int side = idx >= p.rows ? 1 : 0;
+  const int row = idx - side * p.rows;
+  double x[kMaxDim] = {0.0, 0.0, 0.0, 0.0};
+  x[0] = p.origin[0] + ((side ? p.n[0] - 1 : 0) + p.shift[0]) * p.dx;
+  int rr = row;
+#pragma unroll
+  for (int a = 1; a < D; ++a) {
+    const int ia = rr % p.n[a];
+    rr /= p.n[a];
+    x[a] = p.origin[a] + (ia + p.shift[a]) * p.dx;
+  }
+  const double ref = (mode == kFP32) ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
+  const bool half = !wall_full<V>(p);
+  const long long ps = p.pstride;
+  const int want = side ? -1 : 1;
+  double val[q_of(D)];
+  wall_analytic<D, TAN, V>(p, x, t_n, [&](int k) { return p.cv[k][0] == want; },
+                           [](int) { return 0; }, val);
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int cx = vel_comp(D, k, 0);
+    if constexpr (cx == 0) {
+      return;
+    } else {
+      if (cx != want) return;
+      if (mode == kSplit) {
+        p.xdata[((long long)side * S + xface_slot(D, k)) * p.rows + row] = val[k];
+      } else {
+        constexpr int kb = opp_index(D, k);
+        const double wref = (half ? p.omega[k] + p.omega[kb] : p.omega[k]) * ref;
+        buf[k * ps + p.xoff + row] = static_cast<T>(val[k] - wref);
+      }
+    }
+  });
+}
+
+// ------------------------------------------------------------ step kernels --
+
+// Collision of the pulled pre-collision populations (collide_vals, in place)
+// and store of the post-collision ones (collide_store; non-temporal stores:
+// nothing rereads them this step).
+// float64: f*_k = (1-s) f_k + s omega_k phi + dt omega_k R.
+// float32 stores deviations from the uniform exact state omega_k (phi_ref + R t),
+// which is a fixed point of stream + collide, so the deviations follow the same
+// update without the source term; phi is summed with TwoSum compensation.
+template <int D, class T>
+__device__ __forceinline__ void collide_vals(T (&f)[q_of(D)], const KParams& p) {
+  constexpr int Q = q_of(D);
+  if constexpr (std::is_same<T, float>::value) {
+    float sum = f[0], comp = 0.0f;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      float e;
+      two_sum(sum, f[k], sum, e);
+      comp += e;
+    }
+    const float phi = sum + comp;
+    const float oms = 1.0f - p.s_f;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = fmaf(p.s_f * p.omega_f[k], phi, oms * f[k]);
+  } else {
+    double phi = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) phi += f[k];
+    const double oms = 1.0 - p.s;
+    // omega_k (s phi + dt R) + (1 - s) f_k: one uniform constant per
+    // population (omega_k) instead of two (s omega_k, dt R omega_k)
+    const double a = fma(p.s, phi, p.dt * p.R);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = fma(p.omega[k], a, oms * f[k]);
+  }
+}
+
+template <int D, class T>
+__device__ __forceinline__ void collide_store(T (&f)[q_of(D)], T* __restrict__ dst, long long ps,
+                                              int node, const KParams& p) {
+  collide_vals<D, T>(f, p);
+#pragma unroll
+  for (int k = 0; k < q_of(D); ++k) __builtin_nontemporal_store(f[k], dst + k * ps + node);
+}
+
+// Bulk rows: post-collision populations stored (float64, or float32
+// deviations from omega_k (phi_ref + R t_{n+1})).  Rows on a wall of an axis
+// >= 2 are left to k_wall.  On the x_1 faces the unknown populations are read
+// from k_xface's data instead of the upwind node (an index select on the same
+// base address, so the common path keeps its registers); the half-way scheme
+// then subtracts the node's own post-collision kbar value.
+template <int D, class T>
+__device__ __forceinline__ void step_row(const T* __restrict__ src, T* __restrict__ dst,
+                                         const KParams& p, int row) {
+  constexpr int Q = q_of(D);
+  RowInfo<D> r;
+  row_setup<D>(p, row, r);
+  if (r.rowwall) return;
+  const long long ps = p.pstride;
+  const bool half = p.scheme == kHalfWay;
+  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+    col_setup<D>(p, x, r);
+    const int node = r.rowbase + x;
+    const bool xwall = r.lo[0] || r.hi[0];
+    T f[Q];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr int cx = vel_comp(D, k, 0);
+      int idx = node + pull_offset<D, k>(r);
+      if constexpr (cx != 0) {
+        if ((cx == 1) ? r.lo[0] : r.hi[0]) idx = p.xoff + row;
+      }
+      f[k] = src[k * ps + idx];
+    });
+    if (xwall && half) {
+      static_for<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr int cx = vel_comp(D, k, 0);
+        if constexpr (cx != 0) {
+          if ((cx == 1) ? r.lo[0] : r.hi[0]) f[k] -= src[opp_index(D, k) * ps + node];
+        }
+      });
+    }
+    collide_store<D, T>(f, dst, ps, node, p);
+  }
+}
+
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_step(const T* __restrict__ src, T* __restrict__ dst, const KParams p) {
+  const int row = blockIdx.x * blockDim.y + threadIdx.y;
+  if (row >= p.rows) return;
+  step_row<D, T>(src, dst, p, row);
+}
+
+// ------------------------------------------------------ two fused steps --
+//
+// Two time steps t_n -> t_{n+2} in one pass (float32 or float64 storage,
+// d = 3), so each
+// stored population is read and written about once per two steps instead of
+// once per step.  A block owns an x_1-x_2 tile of TX x TY output nodes and
+// a chunk of x_3 planes (fuse_tile), and marches along x_3: for step-1 plane z it updates
+// the tile plus a one-node halo (from A, the state at t_n) into LDS, then
+// updates output plane z - 1 of step 2 by pulling from the LDS planes z - 2,
+// z - 1 and z, and stores it to B.  Each plane's step-1 values stay in LDS only
+// as long as step 2 needs them: populations with c_3 = 0 for two planes, c_3 =
+// +1 for three, c_3 = -1 for one (two with half-way walls, whose x_1 faces need
+// the node's own step-1 value of the opposite population).
+//
+// Rows on a Dirichlet wall of x_2 or x_3 are not updated here.  Their step-1
+// values come from k_wall(A -> C) launched before, and k_wall(C -> B) updates
+// them for step 2 afterwards; for that second launch this kernel also stores
+// its step-1 values of the rows next to those walls in C.  The x_1-face wall
+// data of step 1 are in A's row slots and those of step 2 in B's (k_xface on
+// both before the launch).  Every node goes through exactly the arithmetic of
+// k_step, so the result is bitwise that of two single steps.
+template <class T, bool HALF>
+__global__ void __launch_bounds__((FuseFwdShape<T, HALF>::NT))
+    k_fused2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p,
+             const int zc) {
+  using S = FuseFwdShape<T, HALF>;
+  constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
+  constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  T* lds = reinterpret_cast<T*>(fuse_lds);
+  T* side = lds + S::SLOTS * R;  // half-way only: side[((parity * 2) + face) * RY + ry]
+  const long long ps = p.pstride;
+  const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+  int tx_, ty_, tz_;
+  fuse_tile(p, TX, TY, tx_, ty_, tz_);
+  const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * zc;
+  const int zend = min(zc0 + zc, n2);
+  const int iters = zend - zc0 + 2;
+  for (int it = 0; it < iters; ++it) {
+    const int zp = zc0 - 1 + it;  // step-1 plane of this iteration
+    // ---- step 1 on the tile and its halo of plane zp
+    for (int t = threadIdx.x; t < R; t += NT) {
+      const int r = fuse_region<TX, TY>(t);
+      const int rx = r % RX, ry = r / RX;
+      int gx = x0 - 1 + rx, gy = y0 - 1 + ry, gz = zp;
+      if (gx < 0 || gx >= n0) {
+        if (p.bc[0] != 0) continue;
+        gx = fuse_wrap(gx, n0);
+      }
+      if (gy < 0 || gy >= n1) {
+        if (p.bc[1] != 0) continue;
+        gy = fuse_wrap(gy, n1);
+      }
+      if (gz < 0 || gz >= n2) {
+        if (p.bc[2] != 0) continue;
+        gz = fuse_wrap(gz, n2);
+      }
+      const int row = gz * n1 + gy;
+      RowInfo<D> ri;
+      row_setup_yz(p, gy, gz, ri);
+      col_setup<D>(p, gx, ri);
+      const int node = ri.rowbase + gx;
+      T f[Q];
+      if (ri.rowwall) {
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          f[k] = C[k * ps + node];
+        });
+      } else {
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr int cx = vel_comp(D, k, 0);
+          int idx = node + pull_offset<D, k>(ri);
+          if constexpr (cx != 0) {
+            if ((cx == 1) ? ri.lo[0] : ri.hi[0]) idx = p.xoff + row;
+          }
+          f[k] = A[k * ps + idx];
+        });
+        if (HALF && (ri.lo[0] || ri.hi[0])) {
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] -= A[opp_index(D, k) * ps + node];
+            }
+          });
+        }
+        collide_vals<D, T>(f, p);
+        // rows next to a wall of x_2 / x_3, owned by this block: kept for the
+        // step-2 wall kernel
+        const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
+                         y0 - 1 + ry < n1 && zp >= zc0 && zp < zend;
+        const bool near = (p.bc[1] != 0 && (ri.i[1] == 1 || ri.i[1] == n1 - 2)) ||
+                          (p.bc[2] != 0 && (ri.i[2] == 1 || ri.i[2] == n2 - 2));
+        if (own && near) {
+#pragma unroll
+          for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(f[k], C + k * ps + node);
+        }
+      }
+      static_for<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        lds[fuse_slot<false, k>(it) * R + r] = f[k];
+      });
+      if (HALF && (ri.lo[0] || ri.hi[0])) {
+        // f*_kbar with c_3(kbar) = -1 opposite the face's unknowns, for step 2
+        // of this plane (read one iteration later)
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr int cx = vel_comp(D, k, 0);
+          if constexpr (cx != 0 && vel_comp(D, k, 2) == 1) {
+            const int face = cx == 1 ? 0 : 1;
+            if ((cx == 1) ? ri.lo[0] : ri.hi[0])
+              side[((it & 1) * 2 + face) * RY + ry] = f[opp_index(D, k)];
+          }
+        });
+      }
+    }
+    __syncthreads();
+    // ---- step 2 on output plane zp - 1
+    if (it >= 2) {
+      const int gz = zp - 1;
+      for (int o = threadIdx.x; o < TX * TY; o += NT) {
+        const int ox = o % TX, oy = o / TX;
+        const int gx = x0 + ox, gy = y0 + oy;
+        if (gx >= n0 || gy >= n1) continue;
+        const int row = gz * n1 + gy;
+        RowInfo<D> ri;
+        row_setup_yz(p, gy, gz, ri);
+        if (ri.rowwall) continue;
+        col_setup<D>(p, gx, ri);
+        const int node = ri.rowbase + gx;
+        // every pull from LDS, then the x_1-face unknowns from B's row slots
+        // in a branch of their own (a per-lane choice between the two would
+        // become one generic-pointer load, which waits on all memory traffic)
+        T f[Q];
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr Vec4i c = vel_vec(D, k);
+          constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
+          const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
+          f[k] = lds[fuse_slot<false, k>(it - src_it) * R + rr];
+        });
+        if (ri.lo[0] || ri.hi[0]) {
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] = B[k * ps + p.xoff + row];
+            }
+          });
+        }
+        if (HALF && (ri.lo[0] || ri.hi[0])) {
+          const int own = (oy + 1) * RX + (ox + 1);
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              constexpr int kb = opp_index(D, k);
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                if constexpr (vel_comp(D, k, 2) == 1)
+                  f[k] -= side[(((it - 1) & 1) * 2 + (cx == 1 ? 0 : 1)) * RY + oy + 1];
+                else
+                  f[k] -= lds[fuse_slot<false, kb>(it - 1) * R + own];
+              }
+            }
+          });
+        }
+        collide_store<D, T>(f, B, ps, node, p);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The two-step pass for d = 2: a block owns TX nodes of x_1 and a chunk of
+// x_2 rows and marches along x_2 (rows play the part of the planes of
+// k_fused2, with no halo across x_2 besides the marching itself).  Rows on a
+// Dirichlet wall of x_2 go through C as in k_fused2.
+// One tile (x_1 nodes x0 .. x0 + TX - 1, output rows yc0 .. yend - 1) of the
+// d = 2 two-step pass; lds holds the block's SLOTS x (TX + 2) row-slots.
+template <class T, bool HALF>
+__device__ __forceinline__ void fused2_d2_tile(const T* __restrict__ A, T* __restrict__ B,
+                                               T* __restrict__ C, const KParams& p, T* lds,
+                                               const int x0, const int yc0, const int yend) {
+  using S = FuseShape2<T, HALF>;
+  constexpr int D = 2, Q = q_of(2), TX = S::TX, NT = S::NT;
+  constexpr int R = TX + 2;
+  static_assert(TX == NT, "one output node per thread");
+  const long long ps = p.pstride;
+  const int n0 = p.n[0], n1 = p.n[1];
+  const int iters = yend - yc0 + 2;
+  const int r = threadIdx.x;
+  for (int it = 0; it < iters; ++it) {
+    const int yp = yc0 - 1 + it;  // step-1 row of this iteration
+    // ---- step 1 on the tile and its halo of row yp
+    for (int rr = r; rr < R; rr += NT) {
+      int gx = x0 - 1 + rr, gy = yp;
+      bool skip = false;
+      if (gx < 0 || gx >= n0) {
+        if (p.bc[0] != 0) skip = true;
+        else gx = fuse_wrap(gx, n0);
+      }
+      if (gy < 0 || gy >= n1) {
+        if (p.bc[1] != 0) skip = true;
+        else gy = fuse_wrap(gy, n1);
+      }
+      if (!skip) {
+        const int row = gy;
+        RowInfo<D> ri;
+        row_setup<D>(p, row, ri);
+        col_setup<D>(p, gx, ri);
+        const int node = ri.rowbase + gx;
+        T f[Q];
+        if (ri.rowwall) {
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            f[k] = C[k * ps + node];
+          });
+        } else {
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            int idx = node + pull_offset<D, k>(ri);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) idx = p.xoff + row;
+            }
+            f[k] = A[k * ps + idx];
+          });
+          if (HALF && (ri.lo[0] || ri.hi[0])) {
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] -= A[opp_index(D, k) * ps + node];
+              }
+            });
+          }
+          collide_vals<D, T>(f, p);
+          // rows next to a wall of x_2, owned by this block: kept for the
+          // step-2 wall kernel
+          const bool own = rr >= 1 && rr <= TX && x0 - 1 + rr < n0 && yp >= yc0 && yp < yend;
+          const bool near = p.bc[1] != 0 && (ri.i[1] == 1 || ri.i[1] == n1 - 2);
+          if (own && near) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(f[k], C + k * ps + node);
+          }
+        }
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          lds[fuse_slot2<HALF, k>(it) * R + rr] = f[k];
+        });
+      }
+    }
+    __syncthreads();
+    // ---- step 2 on output row yp - 1
+    if (it >= 2 && r < TX) {
+      const int gy = yp - 1;
+      const int gx = x0 + r;
+      if (gx < n0) {
+        const int row = gy;
+        RowInfo<D> ri;
+        row_setup<D>(p, row, ri);
+        if (!ri.rowwall) {
+          col_setup<D>(p, gx, ri);
+          const int node = ri.rowbase + gx;
+          // pulls from LDS, x_1-face unknowns from B's row slots (as k_fused2)
+          T f[Q];
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr Vec4i c = vel_vec(D, k);
+            constexpr int src_it = c.v[1] == 0 ? 1 : (c.v[1] == 1 ? 2 : 0);
+            f[k] = lds[fuse_slot2<HALF, k>(it - src_it) * R + (r + 1 - c.v[0])];
+          });
+          if (ri.lo[0] || ri.hi[0]) {
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] = B[k * ps + p.xoff + row];
+              }
+            });
+          }
+          if (HALF && (ri.lo[0] || ri.hi[0])) {
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                constexpr int kb = opp_index(D, k);
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0])
+                  f[k] -= lds[fuse_slot2<HALF, kb>(it - 1) * R + (r + 1)];
+              }
+            });
+          }
+          collide_store<D, T>(f, B, ps, node, p);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class T, bool HALF>
+__global__ void __launch_bounds__(256)
+    k_fused2_d2(const T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, const KParams p,
+                const int yc) {
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  int tx_, ty_;
+  fuse_tile2(p, FuseShape2<T, HALF>::TX, tx_, ty_);
+  const int yc0 = ty_ * yc;
+  fused2_d2_tile<T, HALF>(A, B, C, p, reinterpret_cast<T*>(fuse_lds),
+                          tx_ * FuseShape2<T, HALF>::TX, yc0, min(yc0 + yc, p.n[1]));
+}
+
+// Two steps of many periodic d = 2 lattices in one launch: block b takes tile
+// tiles[b] (instance, x_1 start, row range) with the instance's parameter
+// block and buffers (cur selects the source).
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_fused2_d2_batch(const KParams* __restrict__ kps, T* const* __restrict__ bufs,
+                      const BatchTile2* __restrict__ tiles, const int cur) {
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  const BatchTile2 t = tiles[blockIdx.x];
+  fused2_d2_tile<T, false>(bufs[2 * t.inst + cur], bufs[2 * t.inst + 1 - cur], nullptr,
+                           kps[t.inst], reinterpret_cast<T*>(fuse_lds), t.x0, t.y0, t.y1);
+}
+
+// Many lattices in one launch (periodic instances): block b updates rows
+// tiles[b].row0 .. + blockDim.y - 1 of instance tiles[b].inst, whose parameter
+// block is kps[inst] and whose two state buffers are bufs[2 inst], bufs[2 inst + 1]
+// (cur selects the source).
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_step_batch(const KParams* __restrict__ kps, T* const* __restrict__ bufs,
+                 const BatchTile* __restrict__ tiles, const int cur) {
+  const BatchTile t = tiles[blockIdx.x];
+  const KParams& p = kps[t.inst];
+  const int row = t.row0 + threadIdx.y;
+  if (row >= p.rows) return;
+  step_row<D, T>(bufs[2 * t.inst + cur], bufs[2 * t.inst + 1 - cur], p, row);
+}
+
+// Split representation: phi (float64) and g_k = f_k - omega_k phi (float32),
+// pre-collision.  f*_k(y) = omega_k (phi(y) + dt R) + (1 - s) g_k(y), so the
+// pull needs phi and g_k at the upwind node only; arithmetic is float64.
+// Every kernel of the mode evaluates f* with split_fstar_val (two-step passes
+// equal single steps bit for bit), with one uniform constant per population.
+__device__ __forceinline__ double split_fstar_val(double omega, double phi, float g,
+                                                  const KParams& p) {
+  return fma(omega, phi + p.dt * p.R, (1.0 - p.s) * static_cast<double>(g));
+}
+
+template <int D>
+__device__ __forceinline__ void split_pull(double (&f)[q_of(D)], const float* __restrict__ gsrc,
+                                           const double* __restrict__ phisrc, long long ps,
+                                           int node, const RowInfo<D>& r, const KParams& p) {
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    const int idx = node + pull_offset<D, k>(r);
+    f[k] = split_fstar_val(p.omega[k], phisrc[idx], gsrc[k * ps + idx], p);
+  });
+}
+
+template <int D>
+__device__ __forceinline__ double split_fstar(const float* __restrict__ gsrc,
+                                              const double* __restrict__ phisrc, long long ps,
+                                              int node, int kb, const KParams& p) {
+  return split_fstar_val(p.omega[kb], phisrc[node], gsrc[kb * ps + node], p);
+}
+
+template <int D>
+__device__ __forceinline__ void split_store(const double (&f)[q_of(D)], float* __restrict__ gdst,
+                                            double* __restrict__ phidst, long long ps, int node,
+                                            const KParams& p) {
+  constexpr int Q = q_of(D);
+  double phi = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) phi += f[k];
+  __builtin_nontemporal_store(phi, phidst + node);
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    __builtin_nontemporal_store(static_cast<float>(f[k] - p.omega[k] * phi), gdst + k * ps + node);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256)
+    k_step_split(const float* __restrict__ gsrc, float* __restrict__ gdst,
+                 const double* __restrict__ phisrc, double* __restrict__ phidst, const KParams p) {
+  constexpr int Q = q_of(D);
+  constexpr int S = 2 * D - 1;
+  const int row = blockIdx.x * blockDim.y + threadIdx.y;
+  if (row >= p.rows) return;
+  RowInfo<D> r;
+  row_setup<D>(p, row, r);
+  if (r.rowwall) return;
+  const long long ps = p.pstride;
+  const bool half = p.scheme == kHalfWay;
+  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+    col_setup<D>(p, x, r);
+    const int node = r.rowbase + x;
+    double f[Q];
+    split_pull<D>(f, gsrc, phisrc, ps, node, r, p);
+    if (r.lo[0] || r.hi[0]) {
+      const double* W = p.xdata + (r.hi[0] ? S * p.rows : 0) + row;
+      static_for<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr int cx = vel_comp(D, k, 0);
+        if constexpr (cx != 0) {
+          if ((cx == 1) ? r.lo[0] : r.hi[0]) {
+            double v = W[(long long)xface_slot(D, k) * p.rows];
+            if (half) v -= split_fstar<D>(gsrc, phisrc, ps, node, opp_index(D, k), p);
+            f[k] = v;
+          }
+        }
+      });
+    }
+    split_store<D>(f, gdst, phidst, ps, node, p);
+  }
+}
+
+// Two fused steps of the split representation (d = 3), organised as k_fused2:
+// the LDS keeps the step-1 g_k (float32, the same plane slots) and phi
+// (float64, a ring of three planes).  The x_1-face data of step 2 come from a
+// second x-face array (xd2); rows on and next to the walls of x_2 / x_3 go
+// through the scratch state (gC, phiC) as in k_fused2.
+template <bool HALF>
+struct FuseSplitShape;
+template <>
+struct FuseSplitShape<false> {
+  static constexpr int TX = 64, TY = 11, NT = 512, SLOTS = 38;
+};
+template <>
+struct FuseSplitShape<true> {
+  static constexpr int TX = 64, TY = 10, NT = 512, SLOTS = 43;
+};
+
+template <bool HALF>
+__global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
+    k_fused2_split(const float* __restrict__ gA, float* __restrict__ gB, float* __restrict__ gC,
+                   const double* __restrict__ phiA, double* __restrict__ phiB,
+                   double* __restrict__ phiC, const KParams p, const double* __restrict__ xd2,
+                   const int zc) {
+  using S = FuseSplitShape<HALF>;
+  constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
+  constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
+  constexpr int SX = 2 * D - 1;
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  float* lg = reinterpret_cast<float*>(fuse_lds);
+  double* lphi = reinterpret_cast<double*>(fuse_lds + sizeof(float) * S::SLOTS * R);
+  const long long ps = p.pstride;
+  const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+  int tx_, ty_, tz_;
+  fuse_tile(p, TX, TY, tx_, ty_, tz_);
+  const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * zc;
+  const int zend = min(zc0 + zc, n2);
+  const int iters = zend - zc0 + 2;
+  for (int it = 0; it < iters; ++it) {
+    const int zp = zc0 - 1 + it;
+    // plain region order: with two items per thread the halo-column items of
+    // fuse_region would gather one wavefront's loads from every region row in
+    // the second round, with nothing left to overlap them (measured slower)
+    for (int r = threadIdx.x; r < R; r += NT) {
+      const int rx = r % RX, ry = r / RX;
+      int gx = x0 - 1 + rx, gy = y0 - 1 + ry, gz = zp;
+      if (gx < 0 || gx >= n0) {
+        if (p.bc[0] != 0) continue;
+        gx = fuse_wrap(gx, n0);
+      }
+      if (gy < 0 || gy >= n1) {
+        if (p.bc[1] != 0) continue;
+        gy = fuse_wrap(gy, n1);
+      }
+      if (gz < 0 || gz >= n2) {
+        if (p.bc[2] != 0) continue;
+        gz = fuse_wrap(gz, n2);
+      }
+      const int row = gz * n1 + gy;
+      RowInfo<D> ri;
+      row_setup_yz(p, gy, gz, ri);
+      col_setup<D>(p, gx, ri);
+      const int node = ri.rowbase + gx;
+      float g[Q];
+      double phi;
+      if (ri.rowwall) {
+        phi = phiC[node];
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          g[k] = gC[k * ps + node];
+        });
+      } else {
+        double f[Q];
+        split_pull<D>(f, gA, phiA, ps, node, ri, p);
+        if (ri.lo[0] || ri.hi[0]) {
+          const double* W = p.xdata + (ri.hi[0] ? SX * p.rows : 0) + row;
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                double v = W[(long long)xface_slot(D, k) * p.rows];
+                if (HALF) v -= split_fstar<D>(gA, phiA, ps, node, opp_index(D, k), p);
+                f[k] = v;
+              }
+            }
+          });
+        }
+        // split_store's arithmetic, into registers
+        phi = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) phi += f[k];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) g[k] = static_cast<float>(f[k] - p.omega[k] * phi);
+        const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
+                         y0 - 1 + ry < n1 && zp >= zc0 && zp < zend;
+        const bool near = (p.bc[1] != 0 && (ri.i[1] == 1 || ri.i[1] == n1 - 2)) ||
+                          (p.bc[2] != 0 && (ri.i[2] == 1 || ri.i[2] == n2 - 2));
+        if (own && near) {
+          __builtin_nontemporal_store(phi, phiC + node);
+#pragma unroll
+          for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(g[k], gC + k * ps + node);
+        }
+      }
+      static_for<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        lg[fuse_slot<HALF, k>(it) * R + r] = g[k];
+      });
+      lphi[(it % 3) * R + r] = phi;
+    }
+    __syncthreads();
+    if (it >= 2) {
+      const int gz = zp - 1;
+      for (int o = threadIdx.x; o < TX * TY; o += NT) {
+        const int ox = o % TX, oy = o / TX;
+        const int gx = x0 + ox, gy = y0 + oy;
+        if (gx >= n0 || gy >= n1) continue;
+        const int row = gz * n1 + gy;
+        RowInfo<D> ri;
+        row_setup_yz(p, gy, gz, ri);
+        if (ri.rowwall) continue;
+        col_setup<D>(p, gx, ri);
+        const int node = ri.rowbase + gx;
+        double f[Q];
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr Vec4i c = vel_vec(D, k);
+          constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
+          const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
+          const double ph = lphi[((it - src_it) % 3) * R + rr];
+          const float gk = lg[fuse_slot<HALF, k>(it - src_it) * R + rr];
+          f[k] = split_fstar_val(p.omega[k], ph, gk, p);
+        });
+        if (ri.lo[0] || ri.hi[0]) {
+          const double* W = xd2 + (ri.hi[0] ? SX * p.rows : 0) + row;
+          const int own = (oy + 1) * RX + (ox + 1);
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                double v = W[(long long)xface_slot(D, k) * p.rows];
+                if constexpr (HALF) {
+                  constexpr int kb = opp_index(D, k);
+                  const double ph = lphi[((it - 1) % 3) * R + own];
+                  const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
+                  v -= split_fstar_val(p.omega[kb], ph, gb, p);
+                }
+                f[k] = v;
+              }
+            }
+          });
+        }
+        split_store<D>(f, gB, phiB, ps, node, p);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Rows on a wall of an axis >= 2.  Face (a, side), a >= 2, lists the rows
+// with i_a at that side whose indices on the Dirichlet axes 2 <= b < a are
+// interior, so every wall row is visited once; threads run along x_1 as in the
+// bulk kernels, so loads and stores stay coalesced.
+template <int D>
+__device__ __forceinline__ int wall_row(const KParams& p, int idx) {
+  int f = 0;
+  while (f < p.nwfaces - 1 && idx >= p.wface_count[f]) {
+    idx -= p.wface_count[f];
+    ++f;
+  }
+  const int a0 = p.wface_axis[f];
+  int l = idx, row = 0, rstride = 1;
+#pragma unroll
+  for (int b = 1; b < D; ++b) {
+    int ib;
+    if (b == a0) {
+      ib = p.wface_side[f] ? p.n[b] - 1 : 0;
+    } else {
+      const bool inner = (b < a0) && p.bc[b] != 0;
+      const int nb = inner ? p.n[b] - 2 : p.n[b];
+      ib = l % nb + (inner ? 1 : 0);
+      l /= nb;
+    }
+    row += ib * rstride;
+    rstride *= p.n[b];
+  }
+  return row;
+}
+
+template <int D, class T, bool TAN, int V>
+__global__ void __launch_bounds__(256)
+    k_wall(const T* __restrict__ src, T* __restrict__ dst, const KParams p, const double t_n) {
+  constexpr int Q = q_of(D);
+  constexpr bool kF32 = std::is_same<T, float>::value;
+  const int widx = blockIdx.x * blockDim.y + threadIdx.y;
+  if (widx >= p.wall_rows) return;
+  const int row = wall_row<D>(p, widx);
+  RowInfo<D> r;
+  row_setup<D>(p, row, r);
+  const long long ps = p.pstride;
+  // reference of the float32 deviations at t_{n+1}
+  const double ref = kF32 ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
+  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+    col_setup<D>(p, x, r);
+    const int node = r.rowbase + x;
+    T f[Q];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      f[k] = src[k * ps + node + pull_offset<D, k>(r)];
+    });
+    wall_values<D, TAN, V, T>(f, p, r, t_n, ref, [&](int kb) {
+      return static_cast<double>(src[kb * ps + node]) + p.omega[kb] * ref;
+    });
+    collide_store<D, T>(f, dst, ps, node, p);
+  }
+}
+
+template <int D, bool TAN, int V>
+__global__ void __launch_bounds__(256)
+    k_wall_split(const float* __restrict__ gsrc, float* __restrict__ gdst,
+                 const double* __restrict__ phisrc, double* __restrict__ phidst, const KParams p,
+                 const double t_n) {
+  constexpr int Q = q_of(D);
+  const int widx = blockIdx.x * blockDim.y + threadIdx.y;
+  if (widx >= p.wall_rows) return;
+  const int row = wall_row<D>(p, widx);
+  RowInfo<D> r;
+  row_setup<D>(p, row, r);
+  const long long ps = p.pstride;
+  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+    col_setup<D>(p, x, r);
+    const int node = r.rowbase + x;
+    double f[Q];
+    split_pull<D>(f, gsrc, phisrc, ps, node, r, p);
+    wall_values<D, TAN, V, double>(f, p, r, t_n, 0.0, [&](int kb) {
+      return split_fstar<D>(gsrc, phisrc, ps, node, kb, p);
+    });
+    split_store<D>(f, gdst, phidst, ps, node, p);
+  }
+}
+
+// ------------------------------------------------------------ node helpers --
+
+template <int D>
+__device__ __forceinline__ void node_index(const KParams& p, int node, int (&i)[D]) {
+  int rr = node;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    i[a] = rr % p.n[a];
+    rr /= p.n[a];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void node_coords(const KParams& p, const int (&i)[D], double (&x)[D]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = p.origin[a] + (i[a] + p.shift[a]) * p.dx;
+}
+
+// ------------------------------------------------------------------ init ----
+
+template <int D>
+__device__ double fd4_derivative(const double* phi, const KParams& p, const int (&i)[D], int node,
+                                 int a) {
+  const int n = p.n[a];
+  const int st = p.stride[a];
+  auto at = [&](int s) {
+    int j = i[a] + s;
+    j = (j % n + n) % n;
+    return phi[node + (j - i[a]) * st];
+  };
+  return (-at(2) + 8.0 * at(1) - 8.0 * at(-1) + at(-2)) / (12.0 * p.dx);
+}
+
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_init(T* __restrict__ dst, double* __restrict__ phidst, const double* __restrict__ phi0,
+           const double* __restrict__ grad0, const KParams p, int mode) {
+  constexpr int Q = q_of(D);
+  const long long ps = p.pstride;
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
+       node += gridDim.x * blockDim.x) {
+    int i[D];
+    node_index<D>(p, node, i);
+    double phi, grad[D];
+    if (phi0 == nullptr) {
+      double x[D];
+      node_coords<D>(p, i, x);
+      field_initial<D>(p.field, p, x, phi, grad);
+    } else {
+      phi = phi0[node];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        grad[a] = (p.K == 3) ? (grad0 ? grad0[(long long)a * p.nodes + node]
+                                      : fd4_derivative<D>(phi0, p, i, node, a))
+                             : 0.0;
+    }
+    // f_k = omega_k [phi0 + tau dt (u - c_k) . grad phi0]  (eq. ini-simp at tau = 1/2)
+    double f[Q];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr Vec4i c = vel_vec(D, k);
+      double dir = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) dir += (p.u[a] - c.v[a]) * grad[a];
+      f[k] = p.omega[k] * (p.K == 3 ? phi + p.tau * p.dt * dir : phi);
+    });
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) sum += f[k];
+    if (mode == kSplit) {
+      phidst[node] = sum;
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        reinterpret_cast<float*>(dst)[k * ps + node] = static_cast<float>(f[k] - p.omega[k] * sum);
+    } else {
+      // post-collision state at t_0; float32 stores the deviation from
+      // omega_k (phi_ref + R t_1)
+      const double ref = (mode == kFP32) ? p.phi_ref + p.R * p.dt : 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const double fs = (1.0 - p.s) * f[k] + p.s * p.omega[k] * sum + p.dt * p.omega[k] * p.R;
+        dst[k * ps + node] = static_cast<T>(fs - p.omega[k] * ref);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------- moments ----
+
+__device__ __forceinline__ void block_reduce(double (&v)[kNumAcc], double* sh) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < kNumAcc; ++m) sh[m * kRedThreads + tid] = v[m];
+  __syncthreads();
+  for (int half = kRedThreads / 2; half > 0; half >>= 1) {
+    if (tid < half) {
+#pragma unroll
+      for (int m = 0; m < kNumAcc; ++m) {
+        const double a = sh[m * kRedThreads + tid], b = sh[m * kRedThreads + tid + half];
+        sh[m * kRedThreads + tid] = (m == 4) ? fmax(a, b) : a + b;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < kNumAcc; ++m) v[m] = sh[m * kRedThreads];
+}
+
+// accumulators: 0 sum phi, 1 sum phi^2, 2 sum (phi - phi*)^2,
+// 3 sum_k f_k^2 / (2 omega_k), 4 max |phi|, 5 non-finite count
+template <int D, class T>
+__global__ void __launch_bounds__(kRedThreads)
+    k_moments(const T* __restrict__ f, const double* __restrict__ phis, const KParams p,
+              const int mode, const double t_n, double* __restrict__ phi_out,
+              double* __restrict__ partial) {
+  constexpr int Q = q_of(D);
+  __shared__ double sh[kNumAcc * kRedThreads];
+  double acc[kNumAcc] = {0, 0, 0, 0, 0, 0};
+  const long long ps = p.pstride;
+  const bool has_field = p.field.kind != kFieldNone;
+  const double ref = (mode == kFP32) ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
+       node += gridDim.x * blockDim.x) {
+    double fk[Q];
+    double phi;
+    if (mode == kSplit) {
+      phi = phis[node];
+      const float* g = reinterpret_cast<const float*>(f);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) fk[k] = static_cast<double>(g[k * ps + node]) + p.omega[k] * phi;
+    } else {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        fk[k] = static_cast<double>(f[k * ps + node]) + p.omega[k] * ref;
+        sum += fk[k];
+      }
+      phi = sum - p.dt * p.R;
+      // pre-collision populations from the post-collision ones (s != 1)
+      const double inv = 1.0 / (1.0 - p.s);
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        fk[k] = (fk[k] - p.dt * p.omega[k] * p.R - p.s * p.omega[k] * phi) * inv;
+    }
+    double ent = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ent += fk[k] * fk[k] / (2.0 * p.omega[k]);
+    if (phi_out) phi_out[node] = phi;
+    acc[0] += phi;
+    acc[1] += phi * phi;
+    if (has_field) {
+      int i[D];
+      double x[D];
+      node_index<D>(p, node, i);
+      node_coords<D>(p, i, x);
+      const double e = phi - field_value<D>(p.field, p, x, t_n);
+      acc[2] += e * e;
+    }
+    acc[3] += ent;
+    acc[4] = fmax(acc[4], fabs(phi));
+    acc[5] += isfinite(phi) ? 0.0 : 1.0;
+  }
+  block_reduce(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < kNumAcc; ++m) partial[blockIdx.x * kNumAcc + m] = acc[m];
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kRedThreads)
+    k_sum_phi0(const double* __restrict__ arr, const KParams p, double* __restrict__ partial) {
+  __shared__ double sh[kNumAcc * kRedThreads];
+  double acc[kNumAcc] = {0, 0, 0, 0, 0, 0};
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
+       node += gridDim.x * blockDim.x) {
+    double v;
+    if (arr) {
+      v = arr[node];
+    } else {
+      int i[D];
+      double x[D], g[D];
+      node_index<D>(p, node, i);
+      node_coords<D>(p, i, x);
+      field_initial<D>(p.field, p, x, v, g);
+    }
+    acc[0] += v;
+  }
+  block_reduce(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < kNumAcc; ++m) partial[blockIdx.x * kNumAcc + m] = acc[m];
+  }
+}
+
+}  // namespace lbm
