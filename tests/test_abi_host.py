@@ -208,3 +208,11 @@ def test_stability_map_rejects_bad_arguments_before_any_launch():
         assert re.search(msg, lib.lbm_last_error(None).decode())
     # nothing to do: success without touching a device
     assert lib.lbm_stability_map(2, 0, None, None, 0.5, 8, None, None, None, None) == B.OK
+
+
+def test_build_compiles_every_source_once():
+    from paper_2410_13165_amd import build
+    on_disk = sorted(f for f in os.listdir(build.CSRC) if f.endswith(".hip"))
+    assert sorted(build.SOURCES) == on_disk
+    cmd = build.compile_command(build.SOURCES[0], "x.o")
+    assert "--offload-arch=gfx950" in cmd and "-packed-fp32-ops" in cmd and "-c" in cmd
