@@ -241,11 +241,13 @@ int tape_push(lbm_handle* h) {
 }
 
 void tape_clear(lbm_handle* h) {
-  (void)hipStreamSynchronize(h->stream);
+  if (!h->tape_ckpt.empty()) (void)hipStreamSynchronize(h->stream);
   for (void* b : h->tape_ckpt) dev_free(h, b);
   h->tape_ckpt.clear();
   h->tape_active = false;
 }
+
+int set_state_impl(lbm_handle* h, const void* src_dev, int64_t step);
 
 }  // namespace
 
@@ -460,6 +462,8 @@ int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_ph
       if (h->kp.bc[a] != LBM_BC_PERIODIC)
         return fail(h, LBM_EINVAL, "finite-difference gradients need periodic axes");
   }
+  // a tape recorded before belongs to the previous run
+  tape_clear(h);
   int rc = compute_reference(h, phi0_dev);
   if (rc != LBM_OK) return rc;
   hipError_t e = launch_init(h->kp, h->precision, h->buf[0], h->phib[0], phi0_dev, grad_phi0_dev,
@@ -591,6 +595,15 @@ int lbm_get_state(const lbm_handle* h, void* dst_dev) {
 int lbm_set_state(lbm_handle* h, const void* src_dev, int64_t step) {
   if (!h || !src_dev) return fail(nullptr, LBM_EINVAL, "null argument");
   if (step < 0) return fail(h, LBM_EINVAL, "step must be >= 0");
+  if (h->batch_member) return fail(h, LBM_EINVAL, "batch instances take their state from the batch");
+  return set_state_impl(h, src_dev, step);
+}
+
+}  // extern "C"
+
+namespace {
+int set_state_impl(lbm_handle* h, const void* src_dev, int64_t step) {
+  tape_clear(h);
   hipError_t e = hipMemcpyAsync(h->buf[h->cur], src_dev, pop_bytes(h), hipMemcpyDeviceToDevice,
                                 h->stream);
   if (e == hipSuccess && h->precision == LBM_FP32_SPLIT)
@@ -603,7 +616,6 @@ int lbm_set_state(lbm_handle* h, const void* src_dev, int64_t step) {
   return LBM_OK;
 }
 
-namespace {
 void destroy_events(lbm_handle* h) {
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
   h->prof_ev.clear();
@@ -611,6 +623,8 @@ void destroy_events(lbm_handle* h) {
   h->profiling = false;
 }
 }  // namespace
+
+extern "C" {
 
 int lbm_profile_begin(lbm_handle* h, int64_t max_launches) {
   if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
@@ -665,6 +679,7 @@ int lbm_tape_begin(lbm_handle* h, int64_t every) {
   if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
   if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state");
   if (every < 1) return fail(h, LBM_EINVAL, "checkpoint interval must be >= 1");
+  if (h->batch_member) return fail(h, LBM_EINVAL, "batch instances cannot record a tape");
   tape_clear(h);
   h->tape_start = h->step;
   h->tape_every = every;
@@ -695,6 +710,11 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
   const int64_t N = h->step - h->tape_start;
   const int64_t K = h->tape_every;
   const int64_t nseg = (N + K - 1) / K;
+  // segment i starts from checkpoint i; a tape that does not cover the steps
+  // taken since lbm_tape_begin cannot be replayed
+  if (N < 0 || K < 1 || h->tape_ckpt.empty() ||
+      static_cast<int64_t>(h->tape_ckpt.size()) < std::max<int64_t>(nseg, 1))
+    return fail(h, LBM_EINVAL, "the tape does not cover the current step");
   const bool want_tau = dl_dtau_host != nullptr;
   const size_t pb = pop_bytes(h), sb = state_bytes(h);
   const LaunchShape shp = step_shape(kp);
@@ -1150,7 +1170,7 @@ int lbm_batch_tune(lbm_batch* b, int trial_steps, int32_t* config_out, double* m
   for (size_t i = 0; i < b->inst.size() && rc == LBM_OK; ++i) {
     lbm_handle* h = b->inst[i];
     h->cur = cur0;
-    if (lbm_set_state(h, saved[i], step0) != LBM_OK) rc = bfail(b, LBM_EDEVICE, h->err);
+    if (set_state_impl(h, saved[i], step0) != LBM_OK) rc = bfail(b, LBM_EDEVICE, h->err);
   }
   b->cur = cur0;
   b->step = step0;

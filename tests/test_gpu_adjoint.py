@@ -279,3 +279,44 @@ def test_gradient_workload_full_size_identity(prec):
     # products averages out in the inner product (observed ~1e-9); a dropped or
     # mis-signed term changes it at the 1e-2 level
     assert rel <= 1e-6
+
+
+def test_tape_cleared_by_set_state_and_set_initial():
+    """A tape describes the run recorded since lbm_tape_begin: replacing the
+    state (lbm_set_state) or the initial field (lbm_set_initial) drops it, so
+    a later gradient request is refused instead of replaying stale
+    checkpoints."""
+    from paper_2410_13165_amd import LbmError
+    spec = inputs.random_cosines(2, [0.1, 0.1], 0.0, seed=17)
+    lat = gpu_lattice(2, (16, 16), 1.0 / 16, spec)
+    try:
+        seed = torch.zeros(16, 16, dtype=torch.float64, device="cuda")
+        lat.tape_begin(3)
+        lat.step(7)
+        snap = lat.get_state().clone()
+        lat.set_state(snap, 100)
+        with pytest.raises(LbmError, match="tape"):
+            lat.tape_gradient(seed, want_phi0=False, want_tau=True)
+        lat.set_initial(torch.zeros(256, dtype=torch.float64))
+        lat.tape_begin(3)
+        lat.step(5)
+        lat.set_initial(torch.zeros(256, dtype=torch.float64))
+        with pytest.raises(LbmError, match="tape"):
+            lat.tape_gradient(seed, want_phi0=True, want_tau=True)
+    finally:
+        lat.close()
+
+
+def test_batch_instances_refuse_tapes_and_states():
+    from paper_2410_13165_amd import Batch, LbmError
+    specs = [{"dims": (16, 16), "tau": 0.6, "u": [0.1, 0.2], "dx": 1 / 16}] * 2
+    b = Batch(2, specs, precision="fp64")
+    try:
+        b.set_initial(torch.zeros(512, dtype=torch.float64))
+        inst = b.instance(1)
+        with pytest.raises(LbmError, match="batch"):
+            inst.tape_begin(2)
+        with pytest.raises(LbmError, match="batch"):
+            inst.set_state(inst.get_state(), 0)
+    finally:
+        b.close()

@@ -477,3 +477,34 @@ def test_d2q9_fourth_order_convergence_fp64():
     print(f"[convergence] rmse {errs} orders {orders}", flush=True)
     assert all(o > 3.7 for o in orders), orders
     assert abs(orders[-1] - 4.0) <= 0.15, orders
+
+
+# --------------------------------------------------- Example 2 bubble ------
+
+@pytest.mark.parametrize("d,n,K,precision", [(2, 100, 1, "fp64"), (2, 100, 3, "fp64"),
+                                             (3, 40, 3, "fp64"), (2, 100, 3, "fp32_split"),
+                                             (2, 96, 3, "fp32")])
+def test_tanh_bubble_example2(d, n, K, precision):
+    """Example 2: the periodic tanh bubble on [(d-4)/2, (4-d)/2]^d with
+    Rr = 1/(5(d-1)), W = (5-d)/75, initialised in the kernel from the analytic
+    value (K = 1) or value and gradient (K = 3), against the oracle; the RMSE
+    of the device reduction (analytic bubble per node) against the oracle's."""
+    u = [0.05, 0.1, 0.08][:d]
+    spec = inputs.tanh_bubble(d, u)
+    L = 4.0 - d
+    dx = L / n
+    origin = [(d - 4) / 2.0] * d
+    steps = n // 4
+    _check_pair(d, (n,) * d, dx, spec, steps, K=K, origin=origin, precision=precision)
+    run = O.Run(oracle_problem(d, (n,) * d, dx, spec, K=K, origin=origin)).step(steps)
+    lat = gpu_lattice(d, (n,) * d, dx, spec, K=K, origin=origin, precision=precision)
+    try:
+        lat.step(steps)
+        dg = lat.diagnostics()
+    finally:
+        lat.close()
+    print(f"[tanh] d={d} n={n} K={K} {precision}: rmse {dg['rmse']:.6e} oracle {run.rmse():.6e}",
+          flush=True)
+    # |RMSE_gpu - RMSE_oracle| <= RMS of the difference, and phi is O(1) here
+    tol = max(1e-10, 1e-6 * run.rmse()) if precision == "fp64" else TOL[precision]
+    assert abs(dg["rmse"] - run.rmse()) <= tol
