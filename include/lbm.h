@@ -60,7 +60,7 @@ typedef enum {
   LBM_ENOMEM = -2,        /* a device allocation failed                      */
   LBM_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed      */
   LBM_EUNSUPPORTED = -4,  /* valid request this build does not provide       */
-  LBM_ENONFINITE = -5     /* reserved: non-finite values detected            */
+  LBM_ENONFINITE = -5     /* non-finite values detected (lbm_params.check_every) */
 } lbm_status;
 
 /* Boundary condition of one axis (both faces of the axis take the same kind). */
@@ -139,6 +139,12 @@ typedef struct {
                                    time steps per pass of the bulk kernel (bitwise the
                                    same result, about half the HBM traffic); 1: one
                                    step per pass.  Other lattices always use 1.        */
+  int32_t check_every;          /* M > 0: every M steps lbm_step counts the non-finite
+                                   values of one population plane (split mode: phi),
+                                   which any non-finite population of a node reaches
+                                   through the collision; a call that found some
+                                   returns LBM_ENONFINITE.  Calls that ran a check
+                                   synchronise the stream.  0 (default): no checks.   */
 } lbm_params;
 
 typedef struct {
@@ -160,7 +166,7 @@ typedef struct {
 
 /* Fill p with defaults: dx = 1, origin 0, u 0, R 0, g = 1/2, all axes periodic,
    P = 4, K = 3, LBM_FP64, no field, hipMalloc/hipFree, null stream,
-   LBM_WALL_JETS, steps_per_pass = 2. */
+   LBM_WALL_JETS, steps_per_pass = 2, check_every = 0. */
 void lbm_params_default(lbm_params* p);
 
 /* Create a lattice with d in 1..4 axes of dims[0..d-1] nodes and relaxation time
@@ -188,24 +194,37 @@ int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_ph
    the steps go in pairs through one bulk pass that keeps the intermediate
    state in LDS, plus one single step when n is odd; while a tape is recording
    (lbm_tape_begin) pairs are used only with an even checkpoint interval, never
-   across a checkpoint.  The first paired call allocates a
-   scratch state (lbm_state_bytes, plus the x_1-face data of a second step in
-   split mode) through the allocator (LBM_ENOMEM if that fails).  Asynchronous
-   on the stream. */
+   across a checkpoint.  The first paired call allocates, through the
+   allocator, a scratch state (lbm_state_bytes) when the lattice has Dirichlet
+   walls on x_2 or x_3, and in split mode with x_1 walls the x_1-face data of a
+   second step (LBM_ENOMEM if that fails).  Asynchronous on the stream. */
 int lbm_step(lbm_handle* h, int64_t n);
 
-/* Moments of the current state t_n.
-   phi_out_dev (nullable): device float64 buffer of N nodes that receives
+/* Bits of the `what` mask of lbm_moments. */
+typedef enum {
+  LBM_MOM_PHI = 1,        /* the phi field into phi_out_dev                           */
+  LBM_MOM_SUMS = 2,       /* scalars [0], [1], [4], [5]                                */
+  LBM_MOM_RMSE = 4,       /* scalars [2], [6]: evaluates the analytic field per node  */
+  LBM_MOM_ENTROPY = 8,    /* scalar [3]                                               */
+  LBM_MOM_ALL = 15
+} lbm_moment_bits;
+
+/* Moments of the current state t_n, only those selected by `what` (one read
+   of the stored state; the per-node analytic field is evaluated only for
+   LBM_MOM_RMSE).
+   phi_out_dev (LBM_MOM_PHI): device float64 buffer of N nodes that receives
      phi(x, t_n) = sum_k f_k (pre-collision, eq. 0-1-meq).
-   scalars_host (nullable): host buffer of LBM_NSCALARS doubles that receives
+   scalars_host (any scalar bit): host buffer of LBM_NSCALARS doubles that
+   receives, NaN where not selected:
      [0] sum_x phi, [1] sum_x phi^2, [2] sum_x (phi - phi*)^2 (NaN without a field),
      [3] sum_x sum_k f_k^2 / (2 omega_k) over the pre-collision populations
          (NaN when s = 1, where they cannot be recovered from the stored state),
      [4] max_x |phi|, [5] number of non-finite phi values,
-     [6] RMSE of eq. (rmse) = sqrt([2] / N), [7] t_n.
+     [6] RMSE of eq. (rmse) = sqrt([2] / N), [7] t_n (always).
    The reductions are float64 and deterministic; this call synchronises the
-   stream when scalars_host is given. */
-int lbm_moments(lbm_handle* h, double* phi_out_dev, double* scalars_host);
+   stream when a scalar bit is set.  Errors: LBM_EINVAL for unknown bits, a
+   selected output whose pointer is NULL, or no initial state. */
+int lbm_moments(lbm_handle* h, uint32_t what, double* phi_out_dev, double* scalars_host);
 
 int lbm_info(const lbm_handle* h, lbm_info_t* out);
 

@@ -53,6 +53,9 @@ struct lbm_handle {
   int steps_per_pass = 1;
   void* fuse_buf = nullptr;     // state_bytes: populations (+ phi in split mode)
   double* xdata2 = nullptr;     // split mode: x_1-face data of the second step
+  // non-finite checks every check_every steps (0: off)
+  int64_t check_every = 0, last_check = 0;
+  unsigned* nonfinite = nullptr;  // device counter
 };
 
 static thread_local std::string g_create_error;
@@ -104,6 +107,8 @@ void release(lbm_handle* h) {
   }
   dev_free(h, h->partial);
   dev_free(h, h->result);
+  dev_free(h, h->nonfinite);
+  h->nonfinite = nullptr;
   dev_free(h, h->kp.xdata);
   dev_free(h, h->fuse_buf);
   dev_free(h, h->xdata2);
@@ -223,7 +228,7 @@ hipError_t copy_state_out(lbm_handle* h, void* dst) {
 }
 
 double* blob_phi(const lbm_handle* h, void* blob) {
-  return h->precision == LBM_FP32_SPLIT
+  return (h->precision == LBM_FP32_SPLIT && blob)
              ? reinterpret_cast<double*>(static_cast<char*>(blob) + pop_bytes(h))
              : nullptr;
 }
@@ -308,6 +313,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
     return fail(nullptr, LBM_EINVAL, "unknown wall_data");
   if (p->steps_per_pass != 1 && p->steps_per_pass != 2)
     return fail(nullptr, LBM_EINVAL, "steps_per_pass must be 1 or 2");
+  if (p->check_every < 0) return fail(nullptr, LBM_EINVAL, "check_every must be >= 0");
   if (p->wall_data == LBM_WALL_TANGENTIAL)
     for (int a = 0; a < d; ++a)
       if (p->bc[a] != LBM_BC_PERIODIC && !(std::fabs(p->u[a]) > 0.0))
@@ -408,8 +414,11 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   }
   h->partial = static_cast<double*>(dev_alloc(h, sizeof(double) * kRedBlocks * kNumAcc));
   h->result = static_cast<double*>(dev_alloc(h, sizeof(double) * kNumAcc));
+  h->check_every = p->check_every;
+  if (h->check_every > 0) h->nonfinite = static_cast<unsigned*>(dev_alloc(h, 256));
   if (xdata_bytes(h) > 0) kp.xdata = static_cast<double*>(dev_alloc(h, xdata_bytes(h)));
-  bool ok = h->buf[0] && h->buf[1] && h->partial && h->result;
+  bool ok = h->buf[0] && h->buf[1] && h->partial && h->result &&
+            (h->check_every == 0 || h->nonfinite);
   if (xdata_bytes(h) > 0) ok = ok && kp.xdata;
   if (h->precision == LBM_FP32_SPLIT) ok = ok && h->phib[0] && h->phib[1];
   if (!ok) {
@@ -471,28 +480,63 @@ int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_ph
   if (e != hipSuccess) return hip_fail(h, e, "initialisation kernel");
   h->cur = 0;
   h->step = 0;
+  h->last_check = 0;
   h->initialised = true;
   h->init_kind = (h->kp.K == 1) ? 4 : (grad_phi0_dev ? 3 : 2);
   return LBM_OK;
 }
 
-int lbm_step(lbm_handle* h, int64_t n) {
+}  // extern "C"
+
+namespace {
+
+// Checks shared by the stepping entry points.
+int step_checks(lbm_handle* h, int64_t n) {
   if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
   if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
   if (h->batch_member) return fail(h, LBM_EINVAL, "batch instances are stepped by lbm_batch_step");
   if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state (call lbm_set_initial)");
-  // pairs of steps in one bulk pass where the lattice allows it; while a tape
-  // records checkpoints every `every` steps, pairs only when every is even and
-  // the pair starts on an even offset, so that no checkpoint falls inside one
-  const bool pairs =
-      h->steps_per_pass == 2 && (!h->tape_active || h->tape_every % 2 == 0);
-  if (pairs && n >= 2 && !h->fuse_buf) {
-    h->fuse_buf = dev_alloc(h, state_bytes(h));
-    if (!h->fuse_buf) return fail(h, LBM_ENOMEM, "scratch state for two-step passes");
-    if (xdata_bytes(h) > 0) {
-      h->xdata2 = static_cast<double*>(dev_alloc(h, xdata_bytes(h)));
-      if (!h->xdata2) return fail(h, LBM_ENOMEM, "x-face data for two-step passes");
-    }
+  return LBM_OK;
+}
+
+// Pairs of steps in one bulk pass where the lattice allows it; while a tape
+// records checkpoints every `every` steps, pairs only when every is even and
+// the pair starts on an even offset, so that no checkpoint falls inside one.
+bool use_pairs(const lbm_handle* h) {
+  return h->steps_per_pass == 2 && (!h->tape_active || h->tape_every % 2 == 0);
+}
+
+// Scratch state of a two-step pass: the rows on and next to the Dirichlet
+// walls of x_2 / x_3 pass through it, so lattices without such walls need none.
+size_t pair_state_bytes(const lbm_handle* h) {
+  return h->kp.wall_rows > 0 ? state_bytes(h) : 0;
+}
+
+// n steps with the two-step scratch at cbuf (pair_state_bytes) and the split
+// mode's second x_1-face array at xd2 (xdata_bytes).
+// Count the non-finite values of population plane 0 of the stored state
+// (split mode: phi).  Post-collision, f*_0 = (1 - s) f_0 + omega_0 (s phi + dt R)
+// carries every population of its node through phi; with omega_0 = 0 plane 1
+// is counted as well.
+hipError_t check_nonfinite(lbm_handle* h) {
+  if (h->precision == LBM_FP32_SPLIT)
+    return launch_count_nonfinite(h->phib[h->cur], true, h->nodes, h->nonfinite, h->stream);
+  const bool dbl = h->precision == LBM_FP64;
+  const size_t es = elem_size(h->precision);
+  const int planes = h->kp.omega[0] == 0.0 ? 2 : 1;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < planes && e == hipSuccess; ++k)
+    e = launch_count_nonfinite(static_cast<char*>(h->buf[h->cur]) + k * h->kp.pstride * es, dbl,
+                               h->nodes, h->nonfinite, h->stream);
+  return e;
+}
+
+int run_steps(lbm_handle* h, int64_t n, void* cbuf, double* xd2) {
+  const bool pairs = use_pairs(h);
+  bool checked = false;
+  if (h->check_every > 0 && n > 0) {
+    hipError_t e = launch_zero_count(h->nonfinite, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "non-finite counter");
   }
   int64_t i = 0;
   while (i < n) {
@@ -507,8 +551,8 @@ int lbm_step(lbm_handle* h, int64_t n) {
     }
     hipError_t e;
     if (todo == 2) {
-      const FusedBufs fb{h->buf[src], h->buf[dst], h->fuse_buf, h->phib[src], h->phib[dst],
-                         blob_phi(h, h->fuse_buf), h->xdata2};
+      const FusedBufs fb{h->buf[src], h->buf[dst], cbuf, h->phib[src], h->phib[dst],
+                         blob_phi(h, cbuf), xd2};
       e = launch_fused_pair(h->kp, h->precision, fb, h->step, h->stream, ev);
     } else {
       e = launch_step(h->kp, h->precision, h->buf[src], h->buf[dst], h->phib[src],
@@ -522,30 +566,75 @@ int lbm_step(lbm_handle* h, int64_t n) {
       int rc = tape_push(h);
       if (rc != LBM_OK) return rc;
     }
+    if (h->check_every > 0 && h->step - h->last_check >= h->check_every) {
+      e = check_nonfinite(h);
+      if (e != hipSuccess) return hip_fail(h, e, "non-finite check");
+      h->last_check = h->step;
+      checked = true;
+    }
+  }
+  if (checked) {
+    unsigned bad = 0;
+    hipError_t e = hipMemcpyAsync(&bad, h->nonfinite, sizeof(bad), hipMemcpyDeviceToHost,
+                                  h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "non-finite check readback");
+    if (bad > 0)
+      return fail(h, LBM_ENONFINITE,
+                  std::to_string(bad) + " non-finite values in the state by step " +
+                      std::to_string(h->step));
   }
   return LBM_OK;
 }
 
-int lbm_moments(lbm_handle* h, double* phi_out_dev, double* scalars_host) {
+}  // namespace
+
+extern "C" {
+
+int lbm_step(lbm_handle* h, int64_t n) {
+  if (int rc = step_checks(h, n); rc != LBM_OK) return rc;
+  if (use_pairs(h) && n >= 2) {
+    if (pair_state_bytes(h) > 0 && !h->fuse_buf) {
+      h->fuse_buf = dev_alloc(h, pair_state_bytes(h));
+      if (!h->fuse_buf) return fail(h, LBM_ENOMEM, "scratch state for two-step passes");
+    }
+    if (xdata_bytes(h) > 0 && !h->xdata2) {
+      h->xdata2 = static_cast<double*>(dev_alloc(h, xdata_bytes(h)));
+      if (!h->xdata2) return fail(h, LBM_ENOMEM, "x-face data for two-step passes");
+    }
+  }
+  return run_steps(h, n, h->fuse_buf, h->xdata2);
+}
+
+int lbm_moments(lbm_handle* h, uint32_t what, double* phi_out_dev, double* scalars_host) {
   if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+  if (what & ~static_cast<uint32_t>(LBM_MOM_ALL)) return fail(h, LBM_EINVAL, "unknown bits in what");
+  const uint32_t scalar_bits = what & (LBM_MOM_SUMS | LBM_MOM_RMSE | LBM_MOM_ENTROPY);
+  if ((what & LBM_MOM_PHI) && !phi_out_dev)
+    return fail(h, LBM_EINVAL, "LBM_MOM_PHI needs phi_out_dev");
+  if (scalar_bits && !scalars_host)
+    return fail(h, LBM_EINVAL, "scalar moments need scalars_host");
   if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state");
-  if (!phi_out_dev && !scalars_host) return LBM_OK;
+  if (what == 0) return LBM_OK;
   hipError_t e = launch_moments(h->kp, h->precision, h->buf[h->cur], h->phib[h->cur], h->step,
-                                phi_out_dev, h->partial, h->result, h->stream);
+                                (what & LBM_MOM_PHI) ? phi_out_dev : nullptr, h->partial,
+                                h->result, what, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "moments kernel");
-  if (!scalars_host) return LBM_OK;
+  if (!scalar_bits) return LBM_OK;
   double acc[kNumAcc];
   int rc = sync_result(h, acc);
   if (rc != LBM_OK) return rc;
   const double nan = std::numeric_limits<double>::quiet_NaN();
-  const bool has_field = h->kp.field.kind != kFieldNone;
-  scalars_host[0] = acc[0];
-  scalars_host[1] = acc[1];
-  scalars_host[2] = has_field ? acc[2] : nan;
-  scalars_host[3] = (h->precision != LBM_FP32_SPLIT && h->kp.s == 1.0) ? nan : acc[3];
-  scalars_host[4] = acc[4];
-  scalars_host[5] = acc[5];
-  scalars_host[6] = has_field ? std::sqrt(acc[2] / static_cast<double>(h->nodes)) : nan;
+  const bool sums = what & LBM_MOM_SUMS;
+  const bool err = (what & LBM_MOM_RMSE) && h->kp.field.kind != kFieldNone;
+  const bool ent = (what & LBM_MOM_ENTROPY) && (h->precision == LBM_FP32_SPLIT || h->kp.s != 1.0);
+  scalars_host[0] = sums ? acc[0] : nan;
+  scalars_host[1] = sums ? acc[1] : nan;
+  scalars_host[2] = err ? acc[2] : nan;
+  scalars_host[3] = ent ? acc[3] : nan;
+  scalars_host[4] = sums ? acc[4] : nan;
+  scalars_host[5] = sums ? acc[5] : nan;
+  scalars_host[6] = err ? std::sqrt(acc[2] / static_cast<double>(h->nodes)) : nan;
   scalars_host[7] = static_cast<double>(h->step) * h->kp.dt;
   return LBM_OK;
 }
@@ -611,6 +700,7 @@ int set_state_impl(lbm_handle* h, const void* src_dev, int64_t step) {
                        phi_bytes(h), hipMemcpyDeviceToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync");
   h->step = step;
+  h->last_check = step;
   h->initialised = true;
   h->init_kind = 0;
   return LBM_OK;
@@ -1195,7 +1285,8 @@ lbm_handle* lbm_batch_instance(const lbm_batch* b, int i) {
 int lbm_batch_moments(lbm_batch* b, double* scalars_host) {
   if (!b || !scalars_host) return bfail(b, LBM_EINVAL, "null argument");
   for (size_t i = 0; i < b->inst.size(); ++i) {
-    int rc = lbm_moments(b->inst[i], nullptr, scalars_host + i * LBM_NSCALARS);
+    int rc = lbm_moments(b->inst[i], LBM_MOM_SUMS | LBM_MOM_RMSE | LBM_MOM_ENTROPY, nullptr,
+                         scalars_host + i * LBM_NSCALARS);
     if (rc != LBM_OK) return bfail(b, rc, b->inst[i]->err);
   }
   return LBM_OK;

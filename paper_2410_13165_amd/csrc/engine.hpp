@@ -15,6 +15,8 @@ constexpr int kRedBlocks = 1024;  // fixed grid of the deterministic reductions
 constexpr int kRedThreads = 256;
 
 enum Scheme : int { kNoWall = 0, kFullWay = 1, kHalfWay = 2 };
+// work selected by the `what` mask of lbm_moments (the LBM_MOM_* bits)
+enum MomentBits : unsigned { kMomPhi = 1, kMomSums = 2, kMomRmse = 4, kMomEntropy = 8 };
 enum Mode : int { kFP64 = 0, kFP32 = 1, kSplit = 2 };
 enum FieldKind : int { kFieldNone = 0, kFieldCos = 1, kFieldExp = 2, kFieldTanh = 3 };
 
@@ -127,11 +129,19 @@ hipError_t launch_fused_pair(const KParams& p, int mode, const FusedBufs& fb, lo
 hipError_t launch_init(const KParams& p, int mode, void* dst, double* phi_dst,
                        const double* phi0, const double* grad0, hipStream_t stream);
 
-// Moments of the state at step n; writes kRedBlocks x kNumAcc partials, then
-// the final kNumAcc values into out.
+// Moments of the state at step n selected by `what` (MomentBits); with any
+// scalar bit, writes kRedBlocks x kNumAcc partials, then the final kNumAcc
+// values into out.
 hipError_t launch_moments(const KParams& p, int mode, const void* f, const double* phi,
                           long long n, double* phi_out, double* partial, double* out,
-                          hipStream_t stream);
+                          unsigned what, hipStream_t stream);
+
+// Count the non-finite values among n float64 (dbl) or float32 values at
+// `vals` into *count (added); zero_count sets *count = 0 with a kernel (no
+// memset node in a captured graph).
+hipError_t launch_count_nonfinite(const void* vals, bool dbl, long long n, unsigned* count,
+                                  hipStream_t stream);
+hipError_t launch_zero_count(unsigned* count, hipStream_t stream);
 
 // Sum over the nodes of phi0 (analytic when arr == nullptr), into out[0].
 hipError_t launch_sum_phi0(const KParams& p, const double* arr, double* partial,

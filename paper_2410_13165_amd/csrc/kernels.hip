@@ -363,17 +363,18 @@ hipError_t launch_init(const KParams& p, int mode, void* dst, double* phi_dst,
 template <int D>
 static hipError_t moments_d(const KParams& p, int mode, const void* f, const double* phi,
                             long long n, double* phi_out, double* partial, double* out,
-                            hipStream_t stream) {
+                            unsigned what, hipStream_t stream) {
   const double t_n = static_cast<double>(n) * p.dt;
   const dim3 block(kRedThreads), grid(kRedBlocks);
   if (mode == kFP64)
     hipLaunchKernelGGL((k_moments<D, double>), grid, block, 0, stream,
-                       static_cast<const double*>(f), phi, p, mode, t_n, phi_out, partial);
+                       static_cast<const double*>(f), phi, p, mode, t_n, phi_out, partial, what);
   else
     hipLaunchKernelGGL((k_moments<D, float>), grid, block, 0, stream,
-                       static_cast<const float*>(f), phi, p, mode, t_n, phi_out, partial);
+                       static_cast<const float*>(f), phi, p, mode, t_n, phi_out, partial, what);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (!(what & (kMomSums | kMomRmse | kMomEntropy))) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, stream, partial, kRedBlocks,
                      out);
   return hipGetLastError();
@@ -381,14 +382,42 @@ static hipError_t moments_d(const KParams& p, int mode, const void* f, const dou
 
 hipError_t launch_moments(const KParams& p, int mode, const void* f, const double* phi,
                           long long n, double* phi_out, double* partial, double* out,
-                          hipStream_t stream) {
+                          unsigned what, hipStream_t stream) {
   switch (p.d) {
-    case 1: return moments_d<1>(p, mode, f, phi, n, phi_out, partial, out, stream);
-    case 2: return moments_d<2>(p, mode, f, phi, n, phi_out, partial, out, stream);
-    case 3: return moments_d<3>(p, mode, f, phi, n, phi_out, partial, out, stream);
-    case 4: return moments_d<4>(p, mode, f, phi, n, phi_out, partial, out, stream);
+    case 1: return moments_d<1>(p, mode, f, phi, n, phi_out, partial, out, what, stream);
+    case 2: return moments_d<2>(p, mode, f, phi, n, phi_out, partial, out, what, stream);
+    case 3: return moments_d<3>(p, mode, f, phi, n, phi_out, partial, out, what, stream);
+    case 4: return moments_d<4>(p, mode, f, phi, n, phi_out, partial, out, what, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_count_nonfinite(const T* __restrict__ v, long long n, unsigned* __restrict__ count) {
+  unsigned bad = 0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x)
+    bad += isfinite(v[i]) ? 0u : 1u;
+  if (bad) atomicAdd(count, bad);
+}
+
+__global__ void k_zero_count(unsigned* count) { *count = 0u; }
+
+hipError_t launch_count_nonfinite(const void* vals, bool dbl, long long n, unsigned* count,
+                                  hipStream_t stream) {
+  const dim3 grid(grid_for(n, 256)), block(256);
+  if (dbl)
+    hipLaunchKernelGGL((k_count_nonfinite<double>), grid, block, 0, stream,
+                       static_cast<const double*>(vals), n, count);
+  else
+    hipLaunchKernelGGL((k_count_nonfinite<float>), grid, block, 0, stream,
+                       static_cast<const float*>(vals), n, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_count(unsigned* count, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, stream, count);
+  return hipGetLastError();
 }
 
 template <int D>

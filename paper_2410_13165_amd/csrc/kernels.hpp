@@ -1331,16 +1331,22 @@ __device__ __forceinline__ void block_reduce(double (&v)[kNumAcc], double* sh) {
 
 // accumulators: 0 sum phi, 1 sum phi^2, 2 sum (phi - phi*)^2,
 // 3 sum_k f_k^2 / (2 omega_k), 4 max |phi|, 5 non-finite count
+// `what` selects the work (kMom* bits of engine.hpp): without kMomRmse the
+// per-node analytic field is not evaluated, without kMomEntropy the
+// pre-collision populations are not rebuilt, and without any scalar bit no
+// partial sums are written.
 template <int D, class T>
 __global__ void __launch_bounds__(kRedThreads)
     k_moments(const T* __restrict__ f, const double* __restrict__ phis, const KParams p,
               const int mode, const double t_n, double* __restrict__ phi_out,
-              double* __restrict__ partial) {
+              double* __restrict__ partial, const unsigned what) {
   constexpr int Q = q_of(D);
   __shared__ double sh[kNumAcc * kRedThreads];
   double acc[kNumAcc] = {0, 0, 0, 0, 0, 0};
   const long long ps = p.pstride;
-  const bool has_field = p.field.kind != kFieldNone;
+  const bool want_err = (what & kMomRmse) && p.field.kind != kFieldNone;
+  const bool want_ent = (what & kMomEntropy) != 0;
+  const bool want_red = (what & (kMomSums | kMomRmse | kMomEntropy)) != 0;
   const double ref = (mode == kFP32) ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
   for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < p.nodes;
        node += gridDim.x * blockDim.x) {
@@ -1359,19 +1365,25 @@ __global__ void __launch_bounds__(kRedThreads)
         sum += fk[k];
       }
       phi = sum - p.dt * p.R;
-      // pre-collision populations from the post-collision ones (s != 1)
-      const double inv = 1.0 / (1.0 - p.s);
+      if (want_ent) {
+        // pre-collision populations from the post-collision ones (s != 1)
+        const double inv = 1.0 / (1.0 - p.s);
 #pragma unroll
-      for (int k = 0; k < Q; ++k)
-        fk[k] = (fk[k] - p.dt * p.omega[k] * p.R - p.s * p.omega[k] * phi) * inv;
+        for (int k = 0; k < Q; ++k)
+          fk[k] = (fk[k] - p.dt * p.omega[k] * p.R - p.s * p.omega[k] * phi) * inv;
+      }
     }
-    double ent = 0.0;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) ent += fk[k] * fk[k] / (2.0 * p.omega[k]);
     if (phi_out) phi_out[node] = phi;
+    if (!want_red) continue;
+    if (want_ent) {
+      double ent = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) ent += fk[k] * fk[k] / (2.0 * p.omega[k]);
+      acc[3] += ent;
+    }
     acc[0] += phi;
     acc[1] += phi * phi;
-    if (has_field) {
+    if (want_err) {
       int i[D];
       double x[D];
       node_index<D>(p, node, i);
@@ -1379,10 +1391,10 @@ __global__ void __launch_bounds__(kRedThreads)
       const double e = phi - field_value<D>(p.field, p, x, t_n);
       acc[2] += e * e;
     }
-    acc[3] += ent;
     acc[4] = fmax(acc[4], fabs(phi));
     acc[5] += isfinite(phi) ? 0.0 : 1.0;
   }
+  if (!want_red) return;  // uniform over the grid
   block_reduce(acc, sh);
   if (threadIdx.x == 0) {
 #pragma unroll

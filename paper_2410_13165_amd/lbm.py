@@ -23,6 +23,7 @@ MAX_MODES = 16
 NSCALARS = 8
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5
+MOM_PHI, MOM_SUMS, MOM_RMSE, MOM_ENTROPY, MOM_ALL = 1, 2, 4, 8, 15
 BC = {"periodic": 0, "fullway": 1, "halfway": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_split": 2}
 WALL_DATA = {"jets": 0, "tangential": 1}
@@ -50,6 +51,7 @@ class LbmParams(C.Structure):
         ("precision", C.c_int32), ("field", C.POINTER(LbmField)),
         ("alloc", _ALLOC), ("free_fn", _FREE), ("alloc_ctx", C.c_void_p),
         ("stream", C.c_void_p), ("wall_data", C.c_int32), ("steps_per_pass", C.c_int32),
+        ("check_every", C.c_int32),
     ]
 
 
@@ -71,7 +73,7 @@ SIGNATURES = {
                              C.POINTER(C.c_void_p)]),
     "lbm_set_initial": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
-    "lbm_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "lbm_moments": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.POINTER(C.c_double)]),
     "lbm_info": (C.c_int, [C.c_void_p, C.POINTER(LbmInfo)]),
     "lbm_state_bytes": (C.c_int64, [C.c_void_p]),
     "lbm_get_state": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -209,7 +211,7 @@ class Lattice:
                  bc: Optional[Sequence[str]] = None, P: int = 4, K: int = 3,
                  precision: str = "fp64", field=None, g: float = 0.5,
                  m4: Optional[float] = None, wall_data: str = "jets",
-                 steps_per_pass: int = 2, device=None):
+                 steps_per_pass: int = 2, check_every: int = 0, device=None):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -240,6 +242,7 @@ class Lattice:
         self.precision = precision
         p.wall_data = WALL_DATA[wall_data]
         p.steps_per_pass = int(steps_per_pass)
+        p.check_every = int(check_every)
 
         self._field_keep = []
         if field is not None:
@@ -328,12 +331,13 @@ class Lattice:
         """phi(x, t_n) as a float64 tensor shaped (N_d, ..., N_1)."""
         torch = self._torch
         out = torch.empty(self.nodes, dtype=torch.float64, device=self.device)
-        self._check(self.lib.lbm_moments(self._h, C.c_void_p(out.data_ptr()), None))
+        self._check(self.lib.lbm_moments(self._h, MOM_PHI, C.c_void_p(out.data_ptr()), None))
         return out.view(*reversed(self.dims))
 
-    def diagnostics(self) -> dict:
+    def diagnostics(self, what: int = MOM_SUMS | MOM_RMSE | MOM_ENTROPY) -> dict:
+        """FP64 reductions of the current state (NaN for what `what` leaves out)."""
         vals = (C.c_double * NSCALARS)()
-        self._check(self.lib.lbm_moments(self._h, None, vals))
+        self._check(self.lib.lbm_moments(self._h, int(what), None, vals))
         keys = ("sum_phi", "sum_phi2", "sum_err2", "entropy", "max_abs_phi", "nonfinite",
                 "rmse", "t")
         return {k: float(v) for k, v in zip(keys, vals)}

@@ -54,7 +54,7 @@ int main(void) {
   P(lbm_params, bc_order); P(lbm_params, init_order); P(lbm_params, precision);
   P(lbm_params, field); P(lbm_params, alloc); P(lbm_params, free_fn);
   P(lbm_params, alloc_ctx); P(lbm_params, stream); P(lbm_params, wall_data);
-  P(lbm_params, steps_per_pass); P(lbm_info_t, steps_per_pass);
+  P(lbm_params, steps_per_pass); P(lbm_params, check_every); P(lbm_info_t, steps_per_pass);
   P(lbm_field, n_modes); P(lbm_field, amps); P(lbm_field, kvecs); P(lbm_field, phases);
   P(lbm_field, Rr); P(lbm_field, W); P(lbm_field, center);
   P(lbm_info_t, dims); P(lbm_info_t, nodes); P(lbm_info_t, step); P(lbm_info_t, omega);
@@ -89,7 +89,7 @@ def test_params_default():
     assert p.struct_size == C.sizeof(B.LbmParams)
     assert p.dx == 1.0 and p.g == 0.5 and p.bc_order == 4 and p.init_order == 3
     assert p.precision == 0 and list(p.bc) == [0, 0, 0, 0]
-    assert p.wall_data == 0 and p.steps_per_pass == 2
+    assert p.wall_data == 0 and p.steps_per_pass == 2 and p.check_every == 0
 
 
 def _create(d, dims, tau, **kw):
@@ -134,6 +134,8 @@ def test_create_rejects_walls_without_field_and_mixed_schemes():
     assert rc == B.EINVAL and "dx" in err
     rc, h, err = _create(3, (8, 8, 8), 0.5, steps_per_pass=3)
     assert rc == B.EINVAL and "steps_per_pass" in err
+    rc, h, err = _create(3, (8, 8, 8), 0.5, check_every=-1)
+    assert rc == B.EINVAL and "check_every" in err
 
 
 def test_tangential_wall_data_needs_nonzero_normal_velocity():
@@ -160,7 +162,7 @@ def test_tangential_wall_data_needs_nonzero_normal_velocity():
 def test_null_handle_calls_fail_cleanly():
     lib = B.load_library()
     assert lib.lbm_step(None, 1) == B.EINVAL
-    assert lib.lbm_moments(None, None, None) == B.EINVAL
+    assert lib.lbm_moments(None, B.MOM_ALL, None, None) == B.EINVAL
     assert lib.lbm_destroy(None) == B.OK
     assert lib.lbm_state_bytes(None) == -1
 
