@@ -200,6 +200,23 @@ int lbm_set_initial(lbm_handle* h, const double* phi0_dev, const double* grad_ph
    second step (LBM_ENOMEM if that fails).  Asynchronous on the stream. */
 int lbm_step(lbm_handle* h, int64_t n);
 
+/* lbm_step for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, hosts that forbid hipMalloc): the same
+   kernels and bitwise the same result as lbm_step, but the scratch of the
+   two-step passes (the scratch state of lattices with walls on x_2 or x_3,
+   the second x_1-face array in split mode) lives in a fixed device array of
+   the library, 128 MiB per GPU, held from the first lbm_create on that GPU
+   until the process ends.  This call allocates nothing and calls no
+   allocator.  Every lbm_step_static on one GPU uses that same array and
+   leaves its contents behind (nothing in it has to start at zero): calls
+   whose work overlaps on one GPU (lattices stepped concurrently on
+   different streams) race, and must be serialised by the caller.
+   Errors: as lbm_step, plus LBM_EINVAL when the lattice needs more scratch
+   than the array holds (the message gives both sizes) or a tape is
+   recording (its checkpoints are allocated), LBM_EDEVICE when the array's
+   address could not be obtained. */
+int lbm_step_static(lbm_handle* h, int64_t n);
+
 /* Bits of the `what` mask of lbm_moments. */
 typedef enum {
   LBM_MOM_PHI = 1,        /* the phi field into phi_out_dev                           */

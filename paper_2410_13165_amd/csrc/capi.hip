@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,12 +54,53 @@ struct lbm_handle {
   int steps_per_pass = 1;
   void* fuse_buf = nullptr;     // state_bytes: populations (+ phi in split mode)
   double* xdata2 = nullptr;     // split mode: x_1-face data of the second step
+  int device = 0;               // current device at lbm_create
   // non-finite checks every check_every steps (0: off)
   int64_t check_every = 0, last_check = 0;
   unsigned* nonfinite = nullptr;  // device counter
 };
 
 static thread_local std::string g_create_error;
+
+// Scratch of lbm_step_static: a fixed device array that each GPU holds from
+// the library's first use on it until the process ends.  Host code never
+// uses the array's name as an address (on the host it only names the
+// symbol); the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current (static_scratch_setup, from lbm_create).
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Resolve (once) the device address of `scratch` on the current device.
+void static_scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) {
+    g_scratch_ptr[dev] = ptr;
+  } else {
+    g_scratch_err[dev] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+    (void)hipGetLastError();
+  }
+}
+
+void* static_scratch(int dev, hipError_t* err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 namespace {
 
@@ -330,6 +372,10 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
       (p->steps_per_pass == 2 && (d == 3 || (d == 2 && p->precision != LBM_FP32_SPLIT))) ? 2
                                                                                         : 1;
   h->stream = static_cast<hipStream_t>(p->stream);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    (void)hipGetLastError();
+    h->device = -1;
+  }
   h->alloc = p->alloc;
   h->free_fn = p->free_fn;
   h->alloc_ctx = p->alloc_ctx;
@@ -457,6 +503,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
     h->initialised = true;
     h->init_kind = (p->init_order == 1) ? 4 : 1;
   }
+  static_scratch_setup(h->device);
   h->cur = 0;
   h->step = 0;
   *out = h;
@@ -604,6 +651,31 @@ int lbm_step(lbm_handle* h, int64_t n) {
     }
   }
   return run_steps(h, n, h->fuse_buf, h->xdata2);
+}
+
+int lbm_step_static(lbm_handle* h, int64_t n) {
+  if (int rc = step_checks(h, n); rc != LBM_OK) return rc;
+  if (h->tape_active)
+    return fail(h, LBM_EINVAL, "lbm_step_static cannot record a tape (checkpoints are allocated)");
+  void* cbuf = nullptr;
+  double* xd2 = nullptr;
+  if (use_pairs(h) && n >= 2) {
+    const size_t cb = (pair_state_bytes(h) + 255) / 256 * 256;
+    const size_t need = cb + xdata_bytes(h);
+    if (need > kStaticScratchBytes)
+      return fail(h, LBM_EINVAL,
+                  "lbm_step_static needs " + std::to_string(need) +
+                      " bytes of scratch for this lattice; its fixed scratch holds " +
+                      std::to_string(kStaticScratchBytes) + " (use lbm_step)");
+    if (need > 0) {
+      hipError_t err = hipSuccess;
+      void* base = static_scratch(h->device, &err);
+      if (!base) return hip_fail(h, err, "address of the static scratch");
+      if (pair_state_bytes(h) > 0) cbuf = base;
+      if (xdata_bytes(h) > 0) xd2 = reinterpret_cast<double*>(static_cast<char*>(base) + cb);
+    }
+  }
+  return run_steps(h, n, cbuf, xd2);
 }
 
 int lbm_moments(lbm_handle* h, uint32_t what, double* phi_out_dev, double* scalars_host) {

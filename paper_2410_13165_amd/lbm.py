@@ -73,6 +73,7 @@ SIGNATURES = {
                              C.POINTER(C.c_void_p)]),
     "lbm_set_initial": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_step_static": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_moments": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.POINTER(C.c_double)]),
     "lbm_info": (C.c_int, [C.c_void_p, C.POINTER(LbmInfo)]),
     "lbm_state_bytes": (C.c_int64, [C.c_void_p]),
@@ -325,6 +326,11 @@ class Lattice:
 
     def step(self, n: int = 1):
         self._check(self.lib.lbm_step(self._h, int(n)))
+        return self
+
+    def step_static(self, n: int = 1):
+        """lbm_step_static: the same steps without any device allocation."""
+        self._check(self.lib.lbm_step_static(self._h, int(n)))
         return self
 
     def phi(self):
