@@ -287,14 +287,26 @@ int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* st
                tau dependence.  It replays each segment from its checkpoint
                (segment buffers of `every` states), so memory is
                (n_ckpt + every) states; without it no replay is needed.
+     dl_dwall  (host, 2 x n_modes) the gradient with respect to the Dirichlet
+               data: the populations entering through the walls (eq. bun1
+               full-way, the data part of eq. bun2 half-way) are linear in
+               the amplitudes a_j of the analytic field and depend on its
+               phases theta_j, so dl_dwall[j] = dL/da_j and
+               dl_dwall[n_modes + j] = dL/dtheta_j (0 for exponential fields)
+               for the field as it enters the wall data of the steps taken
+               since lbm_tape_begin (the initial state held fixed).  Needs
+               Dirichlet walls and a cos or exp field; the adjoint then runs
+               one step per pass.
    The phi0 outputs need a tape that starts at step 0 right after lbm_create
    with a field or lbm_set_initial.  The handle's state is left unchanged.
-   Errors: LBM_EINVAL (no tape, NULL dl_dphi, phi0 outputs without an initial
-   tape), LBM_EUNSUPPORTED (dL/dtau at s = 1 with post-collision storage),
-   LBM_ENOMEM, LBM_EDEVICE.  lbm_tape_end frees the checkpoints. */
+   Errors: LBM_EINVAL (no tape, a tape that does not cover the current step,
+   NULL dl_dphi, phi0 outputs without an initial tape, dl_dwall without
+   Dirichlet walls or without a cos/exp field), LBM_EUNSUPPORTED (dL/dtau at
+   s = 1 with post-collision storage), LBM_ENOMEM, LBM_EDEVICE.  lbm_tape_end
+   frees the checkpoints; lbm_set_state and lbm_set_initial drop the tape. */
 int lbm_tape_begin(lbm_handle* h, int64_t every);
 int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0_dev,
-                      double* dl_dgrad0_dev, double* dl_dtau_host);
+                      double* dl_dgrad0_dev, double* dl_dtau_host, double* dl_dwall_host);
 int lbm_tape_end(lbm_handle* h);
 
 /* Host-only helper (no device work): the EDF weights of a DdQ(2d^2+1) lattice.

@@ -17,75 +17,16 @@
 
 #include <type_traits>
 
-#include "engine.hpp"
-#include "fuse.hpp"
+#include "kernels.hpp"
 
 namespace lbm {
 
 namespace {
 
-template <int I, int N, class F>
-__device__ __forceinline__ void sfor(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    sfor<I + 1, N>(f);
-  }
-}
-
-struct CV4 {
-  int v[4];
-};
-
-constexpr CV4 cvec(int D, int k) {
-  CV4 r{{0, 0, 0, 0}};
-  for (int a = 0; a < D; ++a) r.v[a] = vel_comp(D, k, a);
-  return r;
-}
-
-template <int D>
-struct Nb {
-  int i[D];
-  int dm[D];  // offset of the node at i_a - 1 (wrapped)
-  int dp[D];  // offset of the node at i_a + 1 (wrapped)
-  bool lo[D];
-  bool hi[D];
-  int rowbase;
-};
-
-template <int D>
-__device__ __forceinline__ void nb_row(const KParams& p, int row, Nb<D>& r) {
-  int rr = row;
-#pragma unroll
-  for (int a = 1; a < D; ++a) {
-    const int n = p.n[a];
-    const int ia = rr % n;
-    rr /= n;
-    const int st = p.stride[a];
-    r.i[a] = ia;
-    r.dm[a] = (ia == 0) ? (n - 1) * st : -st;
-    r.dp[a] = (ia == n - 1) ? -(n - 1) * st : st;
-    const bool wall = p.bc[a] != 0;
-    r.lo[a] = wall && ia == 0;
-    r.hi[a] = wall && ia == n - 1;
-  }
-  r.rowbase = row * p.n[0];
-}
-
-template <int D>
-__device__ __forceinline__ void nb_col(const KParams& p, int x, Nb<D>& r) {
-  const int n0 = p.n[0];
-  r.i[0] = x;
-  r.dm[0] = (x == 0) ? n0 - 1 : -1;
-  r.dp[0] = (x == n0 - 1) ? -(n0 - 1) : 1;
-  const bool wall = p.bc[0] != 0;
-  r.lo[0] = wall && x == 0;
-  r.hi[0] = wall && x == n0 - 1;
-}
-
 // node offset of x + c_k (wrapped) and whether x + c_k leaves the domain
 template <int D, int k>
-__device__ __forceinline__ int push_offset(const Nb<D>& r) {
-  constexpr CV4 c = cvec(D, k);
+__device__ __forceinline__ int push_offset(const RowInfo<D>& r) {
+  constexpr Vec4i c = vel_vec(D, k);
   int off = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -96,8 +37,8 @@ __device__ __forceinline__ int push_offset(const Nb<D>& r) {
 }
 
 template <int D, int k>
-__device__ __forceinline__ bool leaves(const Nb<D>& r) {
-  constexpr CV4 c = cvec(D, k);
+__device__ __forceinline__ bool leaves(const RowInfo<D>& r) {
+  constexpr Vec4i c = vel_vec(D, k);
   bool o = false;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -168,21 +109,21 @@ __global__ void __launch_bounds__(256)
   const int row = blockIdx.x * blockDim.y + threadIdx.y;
   double acc = 0.0;
   if (row < p.rows) {
-    Nb<D> r;
-    nb_row<D>(p, row, r);
+    RowInfo<D> r;
+    row_setup<D>(p, row, r);
     const long long ps = p.pstride;
     const bool half = p.scheme == kHalfWay;
     for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
-      nb_col<D>(p, x, r);
+      col_setup<D>(p, x, r);
       const int node = r.rowbase + x;
       T mu[Q];
-      sfor<0, Q>([&](auto K) {
+      static_for<0, Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
         mu[k] = lsrc[k * ps + node + push_offset<D, k>(r)];
       });
       // populations that leave the domain: zero, or on half-way walls the
       // reflected coupling -lambda_kbar(x) of the wall formula
-      sfor<0, Q>([&](auto K) {
+      static_for<0, Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if (leaves<D, k>(r)) {
           constexpr int kb = opp_index(D, k);
@@ -246,16 +187,16 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
         if (p.bc[2] != 0) continue;
         gz = fuse_wrap(gz, n2);
       }
-      Nb<D> nb;
-      nb_row<D>(p, gz * n1 + gy, nb);
-      nb_col<D>(p, gx, nb);
+      RowInfo<D> nb;
+      row_setup_yz(p, gy, gz, nb);
+      col_setup<D>(p, gx, nb);
       const int node = nb.rowbase + gx;
       T mu[Q];
-      sfor<0, Q>([&](auto K) {
+      static_for<0, Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
         mu[k] = lsrc[k * ps + node + push_offset<D, k>(nb)];
       });
-      sfor<0, Q>([&](auto K) {
+      static_for<0, Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if (leaves<D, k>(nb)) {
           constexpr int kb = opp_index(D, k);
@@ -269,7 +210,7 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
       const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
                        y0 - 1 + ry < n1 && zp >= zc0 && zp < zend;
       if (g1 && own) acc = zdot<D, T>(acc, mu, g1, node, ps, mode, p);
-      sfor<0, Q>([&](auto K) {
+      static_for<0, Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
         lds[adj_slot<HALF, k>(it) * R + r] = oms * mu[k] + ms;
       });
@@ -282,15 +223,15 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
         const int ox = o % TX, oy = o / TX;
         const int gx = x0 + ox, gy = y0 + oy;
         if (gx >= n0 || gy >= n1) continue;
-        Nb<D> nb;
-        nb_row<D>(p, gz * n1 + gy, nb);
-        nb_col<D>(p, gx, nb);
+        RowInfo<D> nb;
+        row_setup_yz(p, gy, gz, nb);
+        col_setup<D>(p, gx, nb);
         const int node = nb.rowbase + gx;
         const int own = (oy + 1) * RX + (ox + 1);
         T mu[Q];
-        sfor<0, Q>([&](auto K) {
+        static_for<0, Q>([&](auto K) {
           constexpr int k = decltype(K)::value;
-          constexpr CV4 c = cvec(D, k);
+          constexpr Vec4i c = vel_vec(D, k);
           constexpr int src_it = c.v[2] == 1 ? 0 : (c.v[2] == 0 ? 1 : 2);
           if (leaves<D, k>(nb)) {
             if constexpr (HALF) {
@@ -370,9 +311,9 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         double h = 0.0;
-        sfor<0, Q>([&](auto K) {
+        static_for<0, Q>([&](auto K) {
           constexpr int k = decltype(K)::value;
-          constexpr CV4 c = cvec(D, k);
+          constexpr Vec4i c = vel_vec(D, k);
           h += p.omega[k] * (p.u[a] - c.v[a]) * l[k];
         });
         dgrad[(long long)a * p.nodes + node] = p.tau * p.dt * h;
@@ -437,6 +378,193 @@ __global__ void __launch_bounds__(256)
   double acc = 0.0;
   for (long long b = threadIdx.x; b < n; b += blockDim.x) acc += partial[b];
   block_sum(acc, sh, out);
+}
+
+// ------------------------------------------------- wall-data sensitivities --
+//
+// The populations that enter through a Dirichlet wall at step n+1 are the
+// wall values W_k(x): full-way, eq. (bun1) at (x, t_{n+1}); half-way, the data
+// part B_k(x_b, t_n) of eq. (bun2) (its -f*_kbar term is part of the linear
+// step above).  For the analytic field F = sum_j a_j cos(kappa_j . y + theta_j)
+// (or a_j exp(kappa_j . y)) every W_k is linear in each amplitude a_j and
+// depends on the phase theta_j through cos / sin, so with
+// lambda^{n+1}_k(x) = dL/df^{n+1}_k(x),
+//   dL/da_j     += sum over unknown (x, k) of lambda^{n+1}_k(x) dW_k(x)/da_j,
+//   dL/dtheta_j += ... dW_k(x)/dtheta_j.
+// The per-mode factors are those of wall_analytic (kernels.hpp): full-way
+//   W_k = omega_k [sum_j a_j (C_j + q_kj S_j) + R t],
+//   q_kj = (dt/2) pv + (dt^3/24) pv^3 (order-dependent),  pv = kappa_j . (c_k - u),
+// with C_j, S_j = cos, sin of kappa_j . (x - u t) + theta_j; half-way
+//   B_k = sum_j a_j [(T0 - T2) C_kj + (T3 - T1) S_kj] + R terms,
+// with C_kj, S_kj at the half-cell-shifted wall point.
+
+// Contributions of one boundary node x (coordinates xc, lk[k] = lambda_k(x)
+// for the unknown k, 0 otherwise) to acc[j] (d/da_j) and acc[kMaxModes + j]
+// (d/dtheta_j).
+template <int D>
+__device__ void wall_param_grad(const KParams& p, const double (&xc)[kMaxDim], double t_n,
+                                const bool (&out)[q_of(D)], const int (&ax)[q_of(D)],
+                                const double (&lk)[q_of(D)], double (&acc)[2 * kMaxModes]) {
+  constexpr int Q = q_of(D);
+  const FieldDev& F = p.field;
+  const double dt = p.dt, dt2 = dt * dt, dt3 = dt2 * dt;
+  const bool full = p.scheme == kFullWay;
+  const bool is_cos = F.kind == kFieldCos;
+  const bool tan = p.wall_data != 0;
+  const double o2 = p.P >= 2 ? 1.0 : 0.0;
+  const double o3 = p.P >= 3 ? 1.0 : 0.0;
+  const double o4 = p.P >= 4 ? 1.0 : 0.0;
+  const double t = full ? t_n + dt : t_n;
+  for (int j = 0; j < F.nmodes; ++j) {
+    double ph = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ph += F.kvec[j][a] * (xc[a] - p.u[a] * t);
+    double C = 0.0, S = 0.0, E = 0.0;
+    if (is_cos)
+      sincos(ph + F.phase[j], &S, &C);
+    else
+      E = exp(ph);
+    const double amp = F.amp[j];
+    const double w = -F.ku[j];
+    double ga = 0.0, gt = 0.0;
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr Vec4i c = vel_vec(D, k);
+      if (!out[k]) return;
+      // kappa_j . c_k, or with tangential wall data its Remark-1 form
+      double pc = 0.0;
+      if (!tan) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) pc += c.v[a] * F.kvec[j][a];
+      } else {
+        double r = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          if (a == ax[k]) r = c.v[a] * p.inv_u[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          if (a != ax[k]) pc += (c.v[a] - r * p.u[a]) * F.kvec[j][a];
+        pc -= r * w;
+      }
+      const double l = lk[k];
+      if (full) {
+        const double pv = pc + w;
+        const double pv3 = pv * pv * pv;
+        if (is_cos) {
+          const double q = o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3;
+          ga += l * p.omega[k] * (C + q * S);
+          gt += l * p.omega[k] * amp * (q * C - S);
+        } else {
+          ga += l * p.omega[k] * E * (1.0 - o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3);
+        }
+      } else {
+        constexpr int kb = opp_index(D, k);
+        const double wp = p.omega[k] + p.omega[kb];
+        const double wm = p.omega[k] - p.omega[kb];
+        const double T0 = wp;
+        const double T1 = o2 * wp * 0.5 * dt * w;
+        const double T2 = -o3 * (wp * dt2 / 8.0 * pc * pc + wm * dt2 / 4.0 * pc * w);
+        const double T3 = -o4 * (wp * (dt3 / 16.0 * pc * pc * w + dt3 / 24.0 * w * w * w) +
+                                 wm * dt3 / 8.0 * pc * w * w);
+        if (is_cos) {
+          double Ck = C, Sk = S;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (c.v[a] == 0) continue;
+            const double cr = F.rot[j][a][0];
+            const double sr = c.v[a] * F.rot[j][a][1];
+            const double nc = Ck * cr + Sk * sr;
+            Sk = Sk * cr - Ck * sr;
+            Ck = nc;
+          }
+          ga += l * ((T0 - T2) * Ck + (T3 - T1) * Sk);
+          gt += l * amp * ((T3 - T1) * Ck - (T0 - T2) * Sk);
+        } else {
+          double Ek = E;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (c.v[a] == 1) Ek *= F.rot[j][a][0];
+            if (c.v[a] == -1) Ek *= F.rot[j][a][1];
+          }
+          ga += l * (T0 + T1 + T2 + T3) * Ek;
+        }
+      }
+    });
+    acc[j] += ga;
+    acc[kMaxModes + j] += gt;
+  }
+}
+
+// One adjoint step's wall-data contractions over every boundary node: the
+// nodes of the rows on a wall of an axis >= 2 (wall_row), then the two x_1-face
+// nodes of every other row.  A fixed grid of kWallGradBlocks blocks walks them;
+// block b adds its sums to partial[b * 2 kMaxModes + m], so the steps'
+// contributions are summed in a fixed order.
+constexpr int kWallGradBlocks = 256;
+
+template <int D, class T>
+__global__ void __launch_bounds__(256)
+    k_wall_grad(const T* __restrict__ lam, const KParams p, const double t_n,
+                double* __restrict__ partial) {
+  constexpr int Q = q_of(D);
+  __shared__ double sh[256];
+  double acc[2 * kMaxModes];
+#pragma unroll
+  for (int m = 0; m < 2 * kMaxModes; ++m) acc[m] = 0.0;
+  const long long ps = p.pstride;
+  const long long nA = static_cast<long long>(p.wall_rows) * p.n[0];
+  const long long nB = p.bc[0] != 0 ? 2LL * p.rows : 0;
+  for (long long it = blockIdx.x * 256LL + threadIdx.x; it < nA + nB; it += 256LL * gridDim.x) {
+    int row, x;
+    if (it < nA) {
+      row = wall_row<D>(p, static_cast<int>(it / p.n[0]));
+      x = static_cast<int>(it % p.n[0]);
+    } else {
+      const long long b = it - nA;
+      row = static_cast<int>(b >> 1);
+      x = (b & 1) ? p.n[0] - 1 : 0;
+    }
+    RowInfo<D> r;
+    row_setup<D>(p, row, r);
+    if (it >= nA && r.rowwall) continue;  // visited among the wall rows
+    col_setup<D>(p, x, r);
+    bool out[Q];
+    int ax[Q];
+    bool any = false;
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      out[k] = outside<D, k>(r);
+      ax[k] = wall_axis<D, k>(r);
+      any = any || out[k];
+    });
+    if (!any) continue;
+    const int node = r.rowbase + x;
+    double lk[Q];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      lk[k] = out[k] ? static_cast<double>(lam[k * ps + node]) : 0.0;
+    });
+    double xc[kMaxDim] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) xc[a] = p.origin[a] + (r.i[a] + p.shift[a]) * p.dx;
+    wall_param_grad<D>(p, xc, t_n, out, ax, lk, acc);
+  }
+  const int M = p.field.nmodes;
+  for (int m = 0; m < M; ++m) {
+    block_sum(acc[m], sh, partial + blockIdx.x * 2 * kMaxModes + m, true);
+    block_sum(acc[kMaxModes + m], sh, partial + blockIdx.x * 2 * kMaxModes + kMaxModes + m, true);
+  }
+}
+
+// out[m] = sum over the blocks b of partial[b * ncols + m], in block order
+__global__ void __launch_bounds__(64)
+    k_sum_columns(const double* __restrict__ partial, int nblocks, int ncols,
+                  double* __restrict__ out) {
+  const int m = threadIdx.x;
+  if (m >= ncols) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[b * ncols + m];
+  out[m] = s;
 }
 
 // --------------------------------------------------------------- launchers --
@@ -575,6 +703,39 @@ hipError_t launch_adjoint_init(const KParams& p, int mode, const void* lam, cons
 hipError_t launch_sum_partials(const double* partial, long long n, double* out,
                                hipStream_t stream) {
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, stream, partial, n, out);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t wall_grad_d(const KParams& p, int mode, const void* lam, double t_n,
+                              double* partial, hipStream_t stream) {
+  const dim3 grid(kWallGradBlocks), block(256);
+  if (mode == kFP64)
+    hipLaunchKernelGGL((k_wall_grad<D, double>), grid, block, 0, stream,
+                       static_cast<const double*>(lam), p, t_n, partial);
+  else
+    hipLaunchKernelGGL((k_wall_grad<D, float>), grid, block, 0, stream,
+                       static_cast<const float*>(lam), p, t_n, partial);
+  return hipGetLastError();
+}
+
+long long wall_grad_partials() { return static_cast<long long>(kWallGradBlocks) * 2 * kMaxModes; }
+
+hipError_t launch_wall_grad(const KParams& p, int mode, const void* lam, long long n,
+                            double* partial, hipStream_t stream) {
+  const double t_n = static_cast<double>(n) * p.dt;
+  switch (p.d) {
+    case 1: return wall_grad_d<1>(p, mode, lam, t_n, partial, stream);
+    case 2: return wall_grad_d<2>(p, mode, lam, t_n, partial, stream);
+    case 3: return wall_grad_d<3>(p, mode, lam, t_n, partial, stream);
+    case 4: return wall_grad_d<4>(p, mode, lam, t_n, partial, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sum_wall_grad(const double* partial, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(64), 0, stream, partial, kWallGradBlocks,
+                     2 * kMaxModes, out);
   return hipGetLastError();
 }
 

@@ -858,10 +858,14 @@ int lbm_tape_end(lbm_handle* h) {
 }
 
 int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0_dev,
-                      double* dl_dgrad0_dev, double* dl_dtau_host) {
+                      double* dl_dgrad0_dev, double* dl_dtau_host, double* dl_dwall_host) {
   if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
   if (!h->tape_active) return fail(h, LBM_EINVAL, "no active tape (call lbm_tape_begin)");
   if (!dl_dphi_dev) return fail(h, LBM_EINVAL, "dL/dphi is NULL");
+  const bool want_wall = dl_dwall_host != nullptr;
+  if (want_wall && (h->kp.scheme == kNoWall ||
+                    (h->kp.field.kind != kFieldCos && h->kp.field.kind != kFieldExp)))
+    return fail(h, LBM_EINVAL, "wall-data gradients need Dirichlet walls fed by a cos or exp field");
   const bool want_init = dl_dphi0_dev || dl_dgrad0_dev;
   const bool at_init = h->tape_start == 0 && h->init_kind != 0;
   if (want_init && !at_init)
@@ -894,8 +898,8 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
   };
   void* lam[2] = {alloc(pb), alloc(pb)};
   // adjoint passes of two steps (d = 3) pair the adjoint steps within each
-  // segment
-  const bool pairs = h->steps_per_pass == 2 && h->d == 3;
+  // segment; the wall-data contractions need every lambda^n, so single steps
+  const bool pairs = h->steps_per_pass == 2 && h->d == 3 && !want_wall;
   const long long npart =
       std::max<long long>(shp.blocks, pairs ? adjoint_pair_blocks(kp, h->precision) : 0);
   double* partial = static_cast<double*>(alloc(sizeof(double) * npart));
@@ -903,10 +907,13 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
   // initialisation's tau term
   double* dsteps = static_cast<double*>(alloc(sizeof(double) * 2));
   double* partial_init = static_cast<double*>(alloc(sizeof(double) * 65536));
+  double* partial_wall =
+      want_wall ? static_cast<double*>(alloc(sizeof(double) * (wall_grad_partials() + 2 * kMaxModes)))
+                : nullptr;
   std::vector<void*> seg;
   if (want_tau && N > 0)
     for (int64_t i = 1; i < std::min<int64_t>(K, N); ++i) seg.push_back(alloc(sb));
-  bool ok = lam[0] && lam[1] && partial && dsteps && partial_init;
+  bool ok = lam[0] && lam[1] && partial && dsteps && partial_init && (!want_wall || partial_wall);
   for (void* b : seg) ok = ok && b;
   if (!ok) {
     cleanup();
@@ -915,6 +922,8 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
   hipError_t e = hipMemsetAsync(lam[0], 0, pb, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(lam[1], 0, pb, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(partial, 0, sizeof(double) * npart, h->stream);
+  if (e == hipSuccess && want_wall)
+    e = hipMemsetAsync(partial_wall, 0, sizeof(double) * wall_grad_partials(), h->stream);
   if (e == hipSuccess) e = launch_adjoint_seed(kp, h->precision, dl_dphi_dev, lam[0], h->stream);
   int cur = 0;
   for (int64_t sgi = nseg - 1; sgi >= 0 && e == hipSuccess; --sgi) {
@@ -943,7 +952,10 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
                                 h->stream);
         n -= 2;
       } else {
-        e = launch_adjoint_step(kp, h->precision, lam[cur], lam[1 - cur], g,
+        // lam[cur] holds lambda^{n+1}: the sensitivities of the wall values of step n+1
+        if (want_wall) e = launch_wall_grad(kp, h->precision, lam[cur], n, partial_wall, h->stream);
+        if (e == hipSuccess)
+          e = launch_adjoint_step(kp, h->precision, lam[cur], lam[1 - cur], g,
                                 want_tau ? blob_phi(h, const_cast<void*>(g)) : nullptr, partial,
                                 h->stream);
         n -= 1;
@@ -980,6 +992,21 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
     if (h->kp.K == 3 && want_tau) {
       e = hipMemcpyAsync(&init_tau, dsteps + 1, sizeof(double), hipMemcpyDeviceToHost,
                          h->stream);
+    }
+  }
+  if (want_wall && e == hipSuccess) {
+    double* sums = partial_wall + wall_grad_partials();
+    double host[2 * kMaxModes];
+    e = launch_sum_wall_grad(partial_wall, sums, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) {
+      const int M = kp.field.nmodes;
+      for (int j = 0; j < M; ++j) {
+        dl_dwall_host[j] = host[j];
+        dl_dwall_host[M + j] = kp.field.kind == kFieldCos ? host[kMaxModes + j] : 0.0;
+      }
     }
   }
   if (want_tau && e == hipSuccess) {

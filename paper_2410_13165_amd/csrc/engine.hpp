@@ -184,6 +184,14 @@ hipError_t launch_adjoint_init(const KParams& p, int mode, const void* lam, cons
                                double* partial, unsigned* nblocks, hipStream_t stream);
 hipError_t launch_sum_partials(const double* partial, long long n, double* out,
                                hipStream_t stream);
+// Wall-data sensitivities of the adjoint step that consumes lambda^{n+1}
+// (lam): adds its contractions with dW/da_j and dW/dtheta_j of the analytic
+// field to partial[0 .. wall_grad_partials()); launch_sum_wall_grad reduces
+// them to out[0 .. 2 kMaxModes) (d/da_j at j, d/dtheta_j at kMaxModes + j).
+long long wall_grad_partials();
+hipError_t launch_wall_grad(const KParams& p, int mode, const void* lam, long long n,
+                            double* partial, hipStream_t stream);
+hipError_t launch_sum_wall_grad(const double* partial, double* out, hipStream_t stream);
 
 // Spectral radius of the amplification matrix over the wave-number grid
 // xi = 2 pi j / m, j in [0, m)^d (nxi = m^d points), for count parameter

@@ -11,28 +11,11 @@
 
 #include "engine.hpp"
 #include "fuse.hpp"
+#include "meta.hpp"
 
 namespace lbm {
 
 // ----------------------------------------------------------------- helpers --
-
-template <int I, int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
-  }
-}
-
-struct Vec4i {
-  int v[4];
-};
-
-constexpr Vec4i vel_vec(int D, int k) {
-  Vec4i r{{0, 0, 0, 0}};
-  for (int a = 0; a < D; ++a) r.v[a] = vel_comp(D, k, a);
-  return r;
-}
 
 template <int D>
 struct RowInfo {

@@ -40,17 +40,10 @@
 
 #include "engine.hpp"
 #include "lattice.hpp"
+#include "meta.hpp"
 
 namespace lbm {
 namespace {
-
-template <int I, int N, class F>
-__device__ __forceinline__ void static_for_q(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for_q<I + 1, N>(f);
-  }
-}
 
 struct cplx {
   double re, im;
@@ -84,7 +77,7 @@ __device__ double rho_at(const double (&w)[q_of(D)], double s, const int (&j)[kM
   double W[Q];
   int cnt[Q];
   int n = 0;
-  static_for_q<0, Q>([&](auto K) {
+  static_for<0, Q>([&](auto K) {
     constexpr int k = decltype(K)::value;
     int ph = 0;
 #pragma unroll

@@ -84,7 +84,7 @@ SIGNATURES = {
                                            C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lbm_tape_begin": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_tape_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                    C.POINTER(C.c_double)]),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lbm_tape_end": (C.c_int, [C.c_void_p]),
     "lbm_profile_begin": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -246,6 +246,7 @@ class Lattice:
         p.check_every = int(check_every)
 
         self._field_keep = []
+        self.n_modes = 0
         if field is not None:
             if isinstance(field, dict):
                 field = Field.from_dict(field)
@@ -257,6 +258,7 @@ class Lattice:
                 ph = np.ascontiguousarray(field.phases if field.phases is not None
                                           else np.zeros(len(amps)), dtype=np.float64)
                 f.n_modes = len(amps)
+                self.n_modes = len(amps)
                 f.amps = amps.ctypes.data_as(C.POINTER(C.c_double))
                 f.kvecs = kv.ctypes.data_as(C.POINTER(C.c_double))
                 f.phases = ph.ctypes.data_as(C.POINTER(C.c_double))
@@ -369,19 +371,24 @@ class Lattice:
         return self
 
     def tape_gradient(self, dl_dphi, want_phi0: bool = True, want_grad0: bool = False,
-                      want_tau: bool = True) -> dict:
-        """Adjoint gradients of L given dL/dphi^N (shape (N_d, ..., N_1))."""
+                      want_tau: bool = True, want_wall: bool = False) -> dict:
+        """Adjoint gradients of L given dL/dphi^N (shape (N_d, ..., N_1)).
+
+        want_wall: dL/da_j and dL/dtheta_j of the analytic field as it enters
+        the Dirichlet data ("wall_amps", "wall_phases")."""
         torch = self._torch
         seed = dl_dphi.to(device=self.device, dtype=torch.float64).contiguous()
         gphi = torch.empty(self.nodes, dtype=torch.float64, device=self.device) if want_phi0 else None
         ggrad = (torch.empty(self.d * self.nodes, dtype=torch.float64, device=self.device)
                  if want_grad0 else None)
         tau = C.c_double()
+        wall = (C.c_double * (2 * MAX_MODES))()
         self._check(self.lib.lbm_tape_gradient(
             self._h, C.c_void_p(seed.data_ptr()),
             C.c_void_p(gphi.data_ptr()) if gphi is not None else None,
             C.c_void_p(ggrad.data_ptr()) if ggrad is not None else None,
-            C.byref(tau) if want_tau else None))
+            C.byref(tau) if want_tau else None,
+            wall if want_wall else None))
         out = {}
         if gphi is not None:
             out["phi0"] = gphi.view(*reversed(self.dims))
@@ -389,6 +396,10 @@ class Lattice:
             out["grad0"] = ggrad.view(self.d, *reversed(self.dims))
         if want_tau:
             out["tau"] = tau.value
+        if want_wall:
+            m = self.n_modes
+            out["wall_amps"] = np.array(wall[:m])
+            out["wall_phases"] = np.array(wall[m:2 * m])
         return out
 
     def profile_begin(self, max_launches: int):
