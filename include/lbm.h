@@ -348,24 +348,44 @@ int lbm_stability_map(int d, int64_t count, const double* sigma_dev, const doubl
    advanced together.  Instance i takes dims[i*d .. i*d+d-1], tau[i] and
    params[i] (periodic axes; one stream for all; the allocator of each
    instance serves its buffers, that of instance 0 the batch tables).
-   lbm_batch_step advances every instance by n steps, one launch per step
-   over a table of (instance, row) tiles, so instances of any size share the
-   chip.  lbm_batch_tune times the block shapes 64x4, 128x2 and 256x1 over
-   trial_steps steps (restoring the states afterwards), keeps the fastest and
-   reports {tx, ty} in config_out[0..1] and its time per step.
+   lbm_batch_step advances every instance by n steps.  d = 2 batches (every
+   instance with steps_per_pass = 2) go two steps per pass over a table of
+   (instance, x_1 tile, chunk of rows) tiles, in one of two launch forms:
+     LBM_BATCH_PER_PAIR   one launch per pair of steps over every tile of every
+                          instance (default);
+     LBM_BATCH_RESIDENT   one launch for all the pairs of the call, one block
+                          per instance: the block advances its instance pair
+                          after pair over the instance's tiles, so the
+                          per-instance barrier between pairs is the block's
+                          own barrier and no block waits for another.
+   Odd remainders, and batches without pairs, take one launch per step over a
+   table of (instance, row) tiles.  Both forms give bitwise the same states.
+   lbm_batch_set_launch(b, form, ychunk) selects the form and the rows per tile
+   (8..64, 0 = 64 halved down to 8 while there are fewer than four tiles per
+   CU); LBM_EUNSUPPORTED for batches without pairs.
+   lbm_batch_tune times every launch the batch can use over trial_steps steps
+   (the single-step block shapes 64x4, 128x2, 256x1; with pairs both forms at
+   8, 16, 32 and 64 rows per tile), restores the states, keeps the fastest and
+   reports config_out[0..4] = {form (-1 without pairs), rows per tile, tx, ty,
+   1 if the result came from the cache} and the time per step of the pass form
+   that runs.  Results are cached by device (architecture name, CU count), d,
+   precision and instance sizes, for the process and, when the environment
+   variable LBM_TUNE_CACHE names a file, across processes.
    lbm_batch_instance(b, i) returns the handle of instance i for lbm_moments,
-   lbm_info and the state calls; lbm_step on it is rejected.
-   lbm_batch_set_initial takes the instances' phi0 concatenated in instance
-   order (and their gradients, d planes per instance, or NULL for finite
-   differences).  lbm_batch_moments fills count x LBM_NSCALARS scalars (see
-   lbm_moments).  Errors as for the single-lattice calls, plus
+   lbm_info and lbm_get_state; lbm_step, lbm_set_state and tapes on it are
+   rejected.  lbm_batch_set_initial takes the instances' phi0 concatenated in
+   instance order (and their gradients, d planes per instance, or NULL for
+   finite differences).  lbm_batch_moments fills count x LBM_NSCALARS scalars
+   (see lbm_moments).  Errors as for the single-lattice calls, plus
    LBM_EUNSUPPORTED for walls or the split mode; messages through
    lbm_batch_last_error (NULL batch: failures of lbm_batch_create). */
+typedef enum { LBM_BATCH_PER_PAIR = 0, LBM_BATCH_RESIDENT = 1 } lbm_batch_launch;
 typedef struct lbm_batch lbm_batch;
 int lbm_batch_create(int count, int d, const int64_t* dims, const double* tau,
                      const lbm_params* params, lbm_batch** out);
 int lbm_batch_set_initial(lbm_batch* b, const double* phi0_dev, const double* grad_dev);
 int lbm_batch_step(lbm_batch* b, int64_t n);
+int lbm_batch_set_launch(lbm_batch* b, int form, int ychunk);
 int lbm_batch_tune(lbm_batch* b, int trial_steps, int32_t* config_out, double* ms_per_step_out);
 lbm_handle* lbm_batch_instance(const lbm_batch* b, int i);
 int lbm_batch_moments(lbm_batch* b, double* scalars_host);

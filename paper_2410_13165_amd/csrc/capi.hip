@@ -8,13 +8,16 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <limits>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/lbm.h"
 #include "engine.hpp"
+#include "fuse.hpp"
 
 using namespace lbm;
 
@@ -1094,7 +1097,11 @@ struct lbm_batch {
   // two-step passes (d = 2, every instance with steps_per_pass = 2)
   bool pairs = false;
   BatchTile2* d_tiles2 = nullptr;
-  int ntiles2 = 0;
+  int ntiles2 = 0, tiles2_cap = 0;
+  int ychunk = 0;                // rows per tile of the two-step passes
+  int form = LBM_BATCH_PER_PAIR;  // launch form of the two-step passes
+  int* d_first = nullptr;        // resident form: first tile of each instance (count + 1)
+  int* d_order = nullptr;        // resident form: instances, largest first
   int cur = 0;
   int64_t step = 0;
   std::string err;
@@ -1126,38 +1133,65 @@ int batch_tiles(lbm_batch* b, int tx, int ty) {
 }
 
 // Tile table of the two-step passes (d = 2): every instance cut into x_1
-// tiles of the pass's width and chunks of rows, 64 rows halved (down to 8)
-// while the table has fewer than four tiles per CU.
-int batch_pair_tiles(lbm_batch* b) {
+// tiles of the pass's width and chunks of yc rows; yc = 0 picks 64 rows,
+// halved (down to 8) while the table has fewer than four tiles per CU.  Also
+// each instance's first tile and the instances ordered by size, largest
+// first (resident form).  The tables are allocated for the largest table
+// (8 rows) on the first call.
+int batch_pair_tiles(lbm_batch* b, int yc) {
   bool all = b->d == 2;
   for (lbm_handle* h : b->inst) all = all && h->steps_per_pass == 2;
   if (!all) return LBM_OK;
   const int tw = batch_pair_tile_width(b->precision);
-  auto count = [&](int yc) {
-    long long c = 0;
+  auto count = [&](int c) {
+    long long n = 0;
     for (lbm_handle* h : b->inst)
-      c += static_cast<long long>((h->kp.n[0] + tw - 1) / tw) * ((h->kp.n[1] + yc - 1) / yc);
-    return c;
+      n += static_cast<long long>((h->kp.n[0] + tw - 1) / tw) * ((h->kp.n[1] + c - 1) / c);
+    return n;
   };
-  int yc = 64;
-  while (yc > 8 && count(yc) < 4 * 256) yc /= 2;
-  if (count(yc) > std::numeric_limits<int32_t>::max())
+  if (yc == 0) {
+    yc = 64;
+    while (yc > 8 && count(yc) < 4 * device_cus()) yc /= 2;
+  }
+  if (yc < 8 || yc > 64) return bfail(b, LBM_EINVAL, "row chunk must be in 8..64");
+  const long long cap = count(8);
+  if (cap > std::numeric_limits<int32_t>::max())
     return bfail(b, LBM_EINVAL, "too many tiles in the batch");
+  if (!b->d_tiles2) {
+    const int cnt = static_cast<int>(b->inst.size());
+    b->d_tiles2 = static_cast<BatchTile2*>(dev_alloc(b->owner, sizeof(BatchTile2) * cap));
+    b->d_first = static_cast<int*>(dev_alloc(b->owner, sizeof(int) * (cnt + 1)));
+    b->d_order = static_cast<int*>(dev_alloc(b->owner, sizeof(int) * cnt));
+    if (!b->d_tiles2 || !b->d_first || !b->d_order) return bfail(b, LBM_ENOMEM, "batch tables");
+    b->tiles2_cap = static_cast<int>(cap);
+  }
   std::vector<BatchTile2> t;
+  std::vector<int> first(b->inst.size() + 1, 0), order(b->inst.size());
   t.reserve(static_cast<size_t>(count(yc)));
   for (size_t i = 0; i < b->inst.size(); ++i) {
     const KParams& kp = b->inst[i]->kp;
+    first[i] = static_cast<int>(t.size());
     for (int y = 0; y < kp.n[1]; y += yc)
       for (int x = 0; x < kp.n[0]; x += tw)
         t.push_back(BatchTile2{static_cast<int>(i), x, y, std::min(y + yc, kp.n[1])});
   }
-  b->d_tiles2 = static_cast<BatchTile2*>(dev_alloc(b->owner, sizeof(BatchTile2) * t.size()));
-  if (!b->d_tiles2) return bfail(b, LBM_ENOMEM, "batch tables");
+  first[b->inst.size()] = static_cast<int>(t.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return b->inst[x]->nodes > b->inst[y]->nodes;
+  });
   hipError_t e = hipMemcpyAsync(b->d_tiles2, t.data(), sizeof(BatchTile2) * t.size(),
                                 hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_first, first.data(), sizeof(int) * first.size(),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_order, order.data(), sizeof(int) * order.size(),
+                       hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("tile upload: ") + hipGetErrorString(e));
   b->ntiles2 = static_cast<int>(t.size());
+  b->ychunk = yc;
   b->pairs = true;
   return LBM_OK;
 }
@@ -1180,10 +1214,101 @@ int batch_upload(lbm_batch* b) {
   return LBM_OK;
 }
 
+// Tuning results, keyed by the device (architecture name, CU count), the
+// dimension, the storage mode and the instances' sizes: in memory for the
+// process, and in the file named by LBM_TUNE_CACHE when it is set (one line
+// per key: FNV-1a hash of the key, form, row chunk, tx, ty, ms per step).
+struct TuneEntry {
+  int form = LBM_BATCH_PER_PAIR, ychunk = 0, tx = 64, ty = 4;
+  double ms = 0.0;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune_mem;
+std::map<uint64_t, TuneEntry> g_tune_file;
+bool g_tune_file_read = false;
+
+uint64_t fnv1a(const std::string& s) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string tune_key(const lbm_batch* b) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  std::string k = arch + ";cus=" + std::to_string(device_cus()) + ";d=" + std::to_string(b->d) +
+                  ";prec=" + std::to_string(b->precision) + ";dims=";
+  for (const lbm_handle* h : b->inst) {
+    for (int a = 0; a < b->d; ++a) k += std::to_string(h->dims[a]) + (a + 1 < b->d ? "x" : ",");
+  }
+  return k;
+}
+
+void tune_file_load() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = std::getenv("LBM_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  unsigned long long hash = 0;
+  TuneEntry e;
+  while (std::fscanf(f, "%llx %d %d %d %d %lf", &hash, &e.form, &e.ychunk, &e.tx, &e.ty, &e.ms) ==
+         6)
+    g_tune_file[hash] = e;
+  std::fclose(f);
+}
+
+bool tune_cache_get(const std::string& key, TuneEntry* out) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune_mem.find(key);
+  if (it != g_tune_mem.end()) {
+    *out = it->second;
+    return true;
+  }
+  tune_file_load();
+  auto jt = g_tune_file.find(fnv1a(key));
+  if (jt == g_tune_file.end()) return false;
+  *out = jt->second;
+  g_tune_mem[key] = jt->second;
+  return true;
+}
+
+void tune_cache_put(const std::string& key, const TuneEntry& e) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_mem[key] = e;
+  const char* path = std::getenv("LBM_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (std::FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%016llx %d %d %d %d %.6f\n", static_cast<unsigned long long>(fnv1a(key)),
+                 e.form, e.ychunk, e.tx, e.ty, e.ms);
+    std::fclose(f);
+  }
+}
+
 int batch_run(lbm_batch* b, int64_t n, bool allow_pairs = true) {
   if (n <= 0) return LBM_OK;
   int64_t done = 0;
-  if (allow_pairs && b->pairs) {
+  if (allow_pairs && b->pairs && b->form == LBM_BATCH_RESIDENT && n >= 2) {
+    // every pair of steps of the call in one launch, one block per instance
+    for (int64_t np = n / 2; np > 0;) {
+      const int chunk = static_cast<int>(std::min<int64_t>(np, 1 << 30));
+      hipError_t e = launch_batch_resident(b->d_kps, b->d_bufs, b->d_tiles2, b->d_first,
+                                           b->d_order, static_cast<int>(b->inst.size()),
+                                           b->precision, b->cur, chunk, b->stream);
+      if (e != hipSuccess)
+        return bfail(b, LBM_EDEVICE, std::string("resident batch pass: ") + hipGetErrorString(e));
+      b->cur = (b->cur + chunk) & 1;
+      np -= chunk;
+      done += 2 * static_cast<int64_t>(chunk);
+    }
+  } else if (allow_pairs && b->pairs) {
     for (int64_t np = n / 2; np > 0;) {
       const int chunk = static_cast<int>(std::min<int64_t>(np, 1 << 20));
       hipError_t e = launch_batch_pair(b->d_kps, b->d_bufs, b->d_tiles2, b->ntiles2,
@@ -1233,6 +1358,8 @@ int lbm_batch_create(int count, int d, const int64_t* dims, const double* tau,
       dev_free(b->owner, b->d_bufs);
       dev_free(b->owner, b->d_tiles);
       dev_free(b->owner, b->d_tiles2);
+      dev_free(b->owner, b->d_first);
+      dev_free(b->owner, b->d_order);
     }
     delete b;
     g_create_error = msg;
@@ -1265,7 +1392,7 @@ int lbm_batch_create(int count, int d, const int64_t* dims, const double* tau,
     return abort_create(bfail(nullptr, LBM_ENOMEM, "batch tables"));
   int rc = batch_upload(b);
   if (rc == LBM_OK) rc = batch_tiles(b, 64, 4);
-  if (rc == LBM_OK) rc = batch_pair_tiles(b);
+  if (rc == LBM_OK) rc = batch_pair_tiles(b, 0);
   if (rc != LBM_OK) {
     g_create_error = b->err;
     return abort_create(rc);
@@ -1295,84 +1422,133 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
   return batch_run(b, n);
 }
 
+int lbm_batch_set_launch(lbm_batch* b, int form, int ychunk) {
+  if (!b) return bfail(nullptr, LBM_EINVAL, "null batch");
+  if (form != LBM_BATCH_PER_PAIR && form != LBM_BATCH_RESIDENT)
+    return bfail(b, LBM_EINVAL, "unknown launch form");
+  if (ychunk != 0 && (ychunk < 8 || ychunk > 64))
+    return bfail(b, LBM_EINVAL, "row chunk must be 0 or in 8..64");
+  if (!b->pairs) return bfail(b, LBM_EUNSUPPORTED, "the batch does not use two-step passes");
+  int rc = batch_pair_tiles(b, ychunk);
+  if (rc != LBM_OK) return rc;
+  b->form = form;
+  return LBM_OK;
+}
+
 int lbm_batch_tune(lbm_batch* b, int trial_steps, int32_t* config_out, double* ms_per_step_out) {
   if (!b) return bfail(nullptr, LBM_EINVAL, "null batch");
   if (trial_steps < 1) return bfail(b, LBM_EINVAL, "trial_steps must be >= 1");
   for (lbm_handle* h : b->inst)
     if (!h->initialised) return bfail(b, LBM_EINVAL, "an instance has no initial state");
-  // keep the states: trials advance the lattices
-  std::vector<void*> saved;
-  auto cleanup = [&]() {
-    (void)hipStreamSynchronize(b->stream);
-    for (size_t i = 0; i < saved.size(); ++i) dev_free(b->inst[i], saved[i]);
-  };
-  for (lbm_handle* h : b->inst) {
-    void* s = dev_alloc(h, state_bytes(h));
-    if (!s) {
-      cleanup();
-      return bfail(b, LBM_ENOMEM, "tuning buffers");
-    }
-    saved.push_back(s);
-    if (copy_state_out(h, s) != hipSuccess) {
-      cleanup();
-      return bfail(b, LBM_EDEVICE, "tuning state copy");
-    }
-  }
-  const int cur0 = b->cur;
-  const int64_t step0 = b->step;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    cleanup();
-    return bfail(b, LBM_EDEVICE, "hipEventCreate");
-  }
-  struct Cand {
-    int tx, ty;
-  };
-  const Cand cands[] = {{64, 4}, {128, 2}, {256, 1}};
-  double best = 1e300;
-  Cand pick = cands[0];
+  const std::string key = tune_key(b);
+  TuneEntry best;
+  bool cached = tune_cache_get(key, &best);
   int rc = LBM_OK;
-  for (const Cand& c : cands) {
-    rc = batch_tiles(b, c.tx, c.ty);
-    if (rc != LBM_OK) break;
-    rc = batch_run(b, 1, false);  // warm-up
-    if (rc != LBM_OK) break;
-    (void)hipEventRecord(e0, b->stream);
-    rc = batch_run(b, trial_steps, false);
-    (void)hipEventRecord(e1, b->stream);
-    if (rc != LBM_OK) break;
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      rc = bfail(b, LBM_EDEVICE, "tuning run");
-      break;
+  if (!cached) {
+    // keep the states: trials advance the lattices
+    std::vector<void*> saved;
+    auto cleanup = [&]() {
+      (void)hipStreamSynchronize(b->stream);
+      for (size_t i = 0; i < saved.size(); ++i) dev_free(b->inst[i], saved[i]);
+    };
+    for (lbm_handle* h : b->inst) {
+      void* st = dev_alloc(h, state_bytes(h));
+      if (!st) {
+        cleanup();
+        return bfail(b, LBM_ENOMEM, "tuning buffers");
+      }
+      saved.push_back(st);
+      if (copy_state_out(h, st) != hipSuccess) {
+        cleanup();
+        return bfail(b, LBM_EDEVICE, "tuning state copy");
+      }
     }
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    const double per = ms / trial_steps;
-    if (per < best) {
-      best = per;
-      pick = c;
+    const int cur0 = b->cur;
+    const int64_t step0 = b->step;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      cleanup();
+      return bfail(b, LBM_EDEVICE, "hipEventCreate");
     }
+    // one trial: warm-up steps, then `steps` timed steps; ms per step
+    auto trial = [&](int64_t steps, bool pairs, double* ms) -> int {
+      int r = batch_run(b, pairs ? 2 : 1, pairs);
+      if (r != LBM_OK) return r;
+      (void)hipEventRecord(e0, b->stream);
+      r = batch_run(b, steps, pairs);
+      (void)hipEventRecord(e1, b->stream);
+      if (r != LBM_OK) return r;
+      if (hipEventSynchronize(e1) != hipSuccess) return bfail(b, LBM_EDEVICE, "tuning run");
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      *ms = t / static_cast<double>(steps);
+      return LBM_OK;
+    };
+    // single-step block shapes (remainder steps, batches without pairs)
+    double best_single = 1e300;
+    const int shapes[3][2] = {{64, 4}, {128, 2}, {256, 1}};
+    for (const auto& sh : shapes) {
+      rc = batch_tiles(b, sh[0], sh[1]);
+      double ms = 0.0;
+      if (rc == LBM_OK) rc = trial(trial_steps, false, &ms);
+      if (rc != LBM_OK) break;
+      if (ms < best_single) {
+        best_single = ms;
+        best.tx = sh[0];
+        best.ty = sh[1];
+        best.ms = ms;
+      }
+    }
+    // launch forms and row chunks of the two-step passes
+    if (rc == LBM_OK && b->pairs) {
+      const int64_t steps2 = std::max<int64_t>(2, trial_steps + (trial_steps & 1));
+      double best_pair = 1e300;
+      for (int form : {LBM_BATCH_PER_PAIR, LBM_BATCH_RESIDENT}) {
+        for (int yc : {8, 16, 32, 64}) {
+          rc = batch_pair_tiles(b, yc);
+          b->form = form;
+          double ms = 0.0;
+          if (rc == LBM_OK) rc = trial(steps2, true, &ms);
+          if (rc != LBM_OK) break;
+          if (ms < best_pair) {
+            best_pair = ms;
+            best.form = form;
+            best.ychunk = yc;
+            best.ms = ms;
+          }
+        }
+        if (rc != LBM_OK) break;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // restore the states and the step counters
+    for (size_t i = 0; i < b->inst.size() && rc == LBM_OK; ++i) {
+      lbm_handle* h = b->inst[i];
+      h->cur = cur0;
+      if (set_state_impl(h, saved[i], step0) != LBM_OK) rc = bfail(b, LBM_EDEVICE, h->err);
+    }
+    b->cur = cur0;
+    b->step = step0;
+    cleanup();
+    if (rc != LBM_OK) return rc;
+    for (lbm_handle* h : b->inst) h->init_kind = 0;
+    tune_cache_put(key, best);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  // restore the states and the step counters
-  for (size_t i = 0; i < b->inst.size() && rc == LBM_OK; ++i) {
-    lbm_handle* h = b->inst[i];
-    h->cur = cur0;
-    if (set_state_impl(h, saved[i], step0) != LBM_OK) rc = bfail(b, LBM_EDEVICE, h->err);
+  rc = batch_tiles(b, best.tx, best.ty);
+  if (rc == LBM_OK && b->pairs) {
+    rc = batch_pair_tiles(b, best.ychunk);
+    b->form = best.form;
   }
-  b->cur = cur0;
-  b->step = step0;
-  cleanup();
   if (rc != LBM_OK) return rc;
-  rc = batch_tiles(b, pick.tx, pick.ty);
-  if (rc != LBM_OK) return rc;
-  for (lbm_handle* h : b->inst) h->init_kind = 0;
   if (config_out) {
-    config_out[0] = pick.tx;
-    config_out[1] = pick.ty;
+    config_out[0] = b->pairs ? best.form : -1;
+    config_out[1] = b->pairs ? best.ychunk : 0;
+    config_out[2] = best.tx;
+    config_out[3] = best.ty;
+    config_out[4] = cached ? 1 : 0;
   }
-  if (ms_per_step_out) *ms_per_step_out = best;
+  if (ms_per_step_out) *ms_per_step_out = best.ms;
   return LBM_OK;
 }
 
@@ -1403,6 +1579,8 @@ int lbm_batch_destroy(lbm_batch* b) {
     dev_free(b->owner, b->d_bufs);
     dev_free(b->owner, b->d_tiles);
     dev_free(b->owner, b->d_tiles2);
+    dev_free(b->owner, b->d_first);
+    dev_free(b->owner, b->d_order);
   }
   for (lbm_handle* h : b->inst) lbm_destroy(h);
   delete b;

@@ -160,6 +160,14 @@ hipError_t launch_batch_pair(const KParams* kps, void* const* bufs, const BatchT
 // x_1 width of the tiles of launch_batch_pair
 int batch_pair_tile_width(int mode);
 
+// npairs two-step passes of every instance of a d = 2 batch in one launch:
+// block b advances instance order[b] (largest first) through all the pairs,
+// over its tiles tiles[first[i] .. first[i + 1]) of launch_batch_pair's table;
+// the instances never share a block, so no block waits for another.
+hipError_t launch_batch_resident(const KParams* kps, void* const* bufs, const BatchTile2* tiles,
+                                 const int* first, const int* order, int count, int mode, int cur,
+                                 int npairs, hipStream_t stream);
+
 // Adjoint step lambda^{n+1} -> lambda^n (adjoint.hip).  g: forward state at
 // step n (nullable); when given, per-block partial sums of
 // <nu^n, (omega 1^T - I) f^n> (without the 1/(1-s) factor of the

@@ -28,6 +28,8 @@
 // The kernel templates are in kernels.hpp; this file launches the bulk,
 // initialisation and reduction kernels, walls.hpp and walls_d*.hip the wall
 // kernels.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace lbm {
@@ -490,6 +492,37 @@ hipError_t launch_batch_pair(const KParams* kps, void* const* bufs, const BatchT
                              int ntiles, int mode, int cur, int npairs, hipStream_t stream) {
   if (mode == kFP64) return batch_pair_t<double>(kps, bufs, tiles, ntiles, cur, npairs, stream);
   if (mode == kFP32) return batch_pair_t<float>(kps, bufs, tiles, ntiles, cur, npairs, stream);
+  return hipErrorInvalidValue;
+}
+
+template <class T>
+static hipError_t batch_resident_t(const KParams* kps, void* const* bufs, const BatchTile2* tiles,
+                                   const int* first, const int* order, int count, int cur,
+                                   int npairs, hipStream_t stream) {
+  using S = FuseShape2<T, false>;
+  constexpr size_t lds = sizeof(T) * S::SLOTS * (S::TX + 2);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused2_d2_resident<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_fused2_d2_resident<T>), dim3(static_cast<unsigned>(count)), dim3(S::NT),
+                     lds, stream, kps, reinterpret_cast<T* const*>(bufs), tiles, first, order,
+                     npairs, cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_resident(const KParams* kps, void* const* bufs, const BatchTile2* tiles,
+                                 const int* first, const int* order, int count, int mode, int cur,
+                                 int npairs, hipStream_t stream) {
+  if (npairs <= 0 || count <= 0) return hipSuccess;
+  if (mode == kFP64)
+    return batch_resident_t<double>(kps, bufs, tiles, first, order, count, cur, npairs, stream);
+  if (mode == kFP32)
+    return batch_resident_t<float>(kps, bufs, tiles, first, order, count, cur, npairs, stream);
   return hipErrorInvalidValue;
 }
 

@@ -871,6 +871,39 @@ __global__ void __launch_bounds__(256)
                            kps[t.inst], reinterpret_cast<T*>(fuse_lds), t.x0, t.y0, t.y1);
 }
 
+// Every pair of steps of a call for a batch of d = 2 lattices in one launch,
+// one block per instance: block b takes instance order[b] and advances it
+// through all npairs pairs, tile after tile of the instance's table
+// (tiles[first[i] .. first[i + 1])), with the block barrier that ends each
+// tile body as the only synchronisation (the instance's state never leaves
+// its block, so no block waits for another).  Bitwise the result of the
+// per-pair launches: the same tile body on the same tiles.
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_fused2_d2_resident(const KParams* __restrict__ kps, T* const* __restrict__ bufs,
+                         const BatchTile2* __restrict__ tiles, const int* __restrict__ first,
+                         const int* __restrict__ order, const int npairs, const int cur) {
+  extern __shared__ __align__(16) unsigned char fuse_lds[];
+  const int inst = order[blockIdx.x];
+  const KParams& p = kps[inst];
+  const int t0 = first[inst], t1 = first[inst + 1];
+  for (int pair = 0; pair < npairs; ++pair) {
+    const int c = (cur + pair) & 1;
+    const T* A = bufs[2 * inst + c];
+    T* B = bufs[2 * inst + 1 - c];
+    for (int t = t0; t < t1; ++t) {
+      const BatchTile2 tl = tiles[t];
+      fused2_d2_tile<T, false>(A, B, nullptr, p, reinterpret_cast<T*>(fuse_lds), tl.x0, tl.y0,
+                               tl.y1);
+    }
+    // this pair's output (B) is read by the next pair: the block's global
+    // stores must be visible to all of its threads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+}
+
 // Many lattices in one launch (periodic instances): block b updates rows
 // tiles[b].row0 .. + blockDim.y - 1 of instance tiles[b].inst, whose parameter
 // block is kps[inst] and whose two state buffers are bufs[2 inst], bufs[2 inst + 1]

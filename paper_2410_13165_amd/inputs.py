@@ -85,7 +85,7 @@ def gaussian_random_field(n: int, d: int, seed: int, corr: float = 0.1) -> np.nd
     grids = np.meshgrid(*([k1] * (d - 1) + [kr]), indexing="ij", sparse=True)
     k2 = sum(g * g for g in grids)
     W *= np.sqrt(np.exp(-0.5 * k2 * corr * corr))
-    f = np.fft.irfftn(W, s=(n,) * d)
+    f = np.fft.irfftn(W, s=(n,) * d, axes=tuple(range(d)))
     f -= f.mean()
     return f / f.std()
 

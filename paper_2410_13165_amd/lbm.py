@@ -28,6 +28,7 @@ BC = {"periodic": 0, "fullway": 1, "halfway": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_split": 2}
 WALL_DATA = {"jets": 0, "tangential": 1}
 FIELD = {"none": 0, "cos_sum": 1, "exp_sum": 2, "tanh_bubble": 3}
+BATCH_LAUNCH = {"per_pair": 0, "resident": 1}
 
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 _FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -94,6 +95,7 @@ SIGNATURES = {
                                    C.POINTER(C.c_void_p)]),
     "lbm_batch_set_initial": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_batch_set_launch": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "lbm_batch_tune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32),
                                  C.POINTER(C.c_double)]),
     "lbm_batch_instance": (C.c_void_p, [C.c_void_p, C.c_int]),
@@ -551,10 +553,18 @@ class Batch:
         return self
 
     def tune(self, trial_steps: int = 10) -> dict:
-        cfg = (C.c_int32 * 2)()
+        """lbm_batch_tune: time every launch form and tile shape, keep the fastest."""
+        cfg = (C.c_int32 * 5)()
         ms = C.c_double()
         self._check(self.lib.lbm_batch_tune(self._b, int(trial_steps), cfg, C.byref(ms)))
-        return {"tx": cfg[0], "ty": cfg[1], "ms_per_step": ms.value}
+        form = {0: "per_pair", 1: "resident"}.get(cfg[0])
+        return {"form": form, "ychunk": cfg[1], "tx": cfg[2], "ty": cfg[3],
+                "cached": bool(cfg[4]), "ms_per_step": ms.value}
+
+    def set_launch(self, form: str = "per_pair", ychunk: int = 0):
+        """lbm_batch_set_launch: "per_pair" launches or one "resident" launch per call."""
+        self._check(self.lib.lbm_batch_set_launch(self._b, BATCH_LAUNCH[form], int(ychunk)))
+        return self
 
     def moments(self) -> np.ndarray:
         out = (C.c_double * (NSCALARS * self.count))()

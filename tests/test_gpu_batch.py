@@ -52,6 +52,11 @@ def test_batch_matches_oracle_per_instance(precision, tol, K):
             assert rel_l2(got, run.phi()) <= tol, (i, sp)
 
 
+@pytest.mark.skip(reason="runs lbm_batch_tune with the ordered-queue persistent form, which "
+                         "stalled inside the tuner on MI355X twice (once with time-only wait "
+                         "bounds, once with poll bounds and system-scope counters) with no cause "
+                         "found by reading; that form is switched off, so this test stays off "
+                         "the GPU")
 def test_tuner_restores_state_and_configs_agree():
     """Every block shape gives bitwise identical states; tuning leaves the
     state where it was."""
@@ -172,3 +177,180 @@ def test_sweep_workload_full_size():
             run = O.Run(prob, phi0=to_oracle_order(part)).step(steps)
             got = to_oracle_order(b.instance(i).phi().cpu().numpy())
             assert rel_l2(got, run.phi()) <= 2e-5, (i, sp)
+
+
+@pytest.mark.skip(reason="the ordered-queue persistent form it drives stalled on MI355X twice "
+                         "and is switched off (lbm_batch_set_launch no longer offers it)")
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("ychunk", [8, 64])
+def test_persistent_launch_equals_per_pair_launches(precision, ychunk):
+    """Every pair of steps of a call in one persistent launch (blocks claim
+    (pair, tile) items from an ordered queue and wait on per-instance
+    completion counters): bitwise the states of one launch per pair, odd
+    step counts included, over instances of very different sizes."""
+    from paper_2410_13165_amd import Batch
+    rng = np.random.default_rng(46)
+    specs = _specs(rng, 13, [16, 64, 300, 520], (0.5, 1.6), (-0.4, 0.4))
+    parts, phi0 = _concat_phi0(specs, 850)
+    with Batch(2, specs, precision=precision) as a, Batch(2, specs, precision=precision) as b:
+        a.set_initial(phi0)
+        b.set_initial(phi0)
+        b.set_launch("persistent", ychunk)
+        print(f"[persist] {precision} ychunk={ychunk}", flush=True)
+        for n in (2, 7, 40):
+            a.step(n)
+            b.step(n)
+            for i in range(len(specs)):
+                assert torch.equal(a.instance(i).phi(), b.instance(i).phi()), (n, i)
+            assert b.instance(0).info()["step"] == a.instance(0).info()["step"]
+
+
+@pytest.mark.skip(reason="the ordered-queue persistent form it drives stalled on MI355X twice "
+                         "and is switched off (lbm_batch_set_launch no longer offers it)")
+def test_sweep_workload_persistent_full_size():
+    """The full stability-sweep workload (512 instances, fp32) in one persistent
+    launch per call: bitwise the per-pair launches after 10 steps, and one
+    instance of each size against its oracle run."""
+    from paper_2410_13165_amd import Batch
+    specs = inputs.sweep_specs()
+    phi0 = torch.from_numpy(inputs.sweep_phi0(specs))
+    steps = 10
+    picks = {}
+    for i, sp in enumerate(specs):
+        picks.setdefault(sp["dims"][0], i)
+    with Batch(2, specs, precision="fp32") as a, Batch(2, specs, precision="fp32") as b:
+        a.set_initial(phi0)
+        b.set_initial(phi0)
+        b.set_launch("persistent")
+        a.step(steps)
+        b.step(steps)
+        for i in range(len(specs)):
+            assert torch.equal(a.instance(i).phi(), b.instance(i).phi()), i
+        offs = np.concatenate([[0], np.cumsum([int(np.prod(sp["dims"])) for sp in specs])])
+        for n, i in sorted(picks.items()):
+            sp = specs[i]
+            prob = oracle_problem(2, sp["dims"], sp["dx"], None, u=sp["u"], tau=sp["tau"],
+                                  K=sp["K"])
+            part = phi0.numpy()[offs[i]:offs[i + 1]].reshape(tuple(reversed(sp["dims"])))
+            run = O.Run(prob, phi0=to_oracle_order(part)).step(steps)
+            got = to_oracle_order(b.instance(i).phi().cpu().numpy())
+            assert rel_l2(got, run.phi()) <= 2e-5, (i, sp)
+
+
+@pytest.mark.skip(reason="runs lbm_batch_tune with the ordered-queue persistent form, which "
+                         "stalled inside the tuner on MI355X twice (once with time-only wait "
+                         "bounds, once with poll bounds and system-scope counters) with no cause "
+                         "found by reading; that form is switched off, so this test stays off "
+                         "the GPU")
+def test_tuner_covers_launch_forms_and_caches(tmp_path, monkeypatch):
+    """The tuner times the launches the steps use (launch form and rows per
+    tile of the two-step passes), reports the one it keeps, and serves the same
+    batch shape from its cache afterwards (in memory, and appended to the file
+    named by LBM_TUNE_CACHE)."""
+    from paper_2410_13165_amd import Batch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LBM_TUNE_CACHE", str(cache))
+    rng = np.random.default_rng(47)
+    specs = _specs(rng, 6, [48, 96], (0.6, 1.2), (-0.3, 0.3))
+    specs[0]["dims"] = (77, 51)  # a shape no other test tunes
+    parts, phi0 = _concat_phi0(specs, 870)
+    with Batch(2, specs, precision="fp32") as b:
+        b.set_initial(phi0)
+        cfg = b.tune(4)
+        print("[batch] tuned", cfg, flush=True)
+        assert cfg["form"] in ("per_pair", "persistent") and 8 <= cfg["ychunk"] <= 64
+        assert not cfg["cached"]
+        again = b.tune(4)
+        assert again["cached"] and again["form"] == cfg["form"] and again["ychunk"] == cfg["ychunk"]
+    lines = cache.read_text().split()
+    assert len(lines) == 6 and int(lines[2]) == cfg["ychunk"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("ychunk", [8, 64])
+def test_resident_launch_equals_per_pair_launches(precision, ychunk):
+    """Every pair of steps of a call in one launch with one block per instance
+    (the block walks its instance's tiles pair after pair; no block waits for
+    another): bitwise the states of one launch per pair, odd step counts
+    included, over instances of very different sizes."""
+    from paper_2410_13165_amd import Batch
+    rng = np.random.default_rng(48)
+    specs = _specs(rng, 13, [16, 64, 300, 520], (0.5, 1.6), (-0.4, 0.4))
+    parts, phi0 = _concat_phi0(specs, 880)
+    with Batch(2, specs, precision=precision) as a, Batch(2, specs, precision=precision) as b:
+        a.set_initial(phi0)
+        b.set_initial(phi0)
+        b.set_launch("resident", ychunk)
+        print(f"[resident] {precision} ychunk={ychunk}", flush=True)
+        for n in (2, 7, 40):
+            a.step(n)
+            b.step(n)
+            for i in range(len(specs)):
+                assert torch.equal(a.instance(i).phi(), b.instance(i).phi()), (n, i)
+            assert b.instance(0).info()["step"] == a.instance(0).info()["step"]
+
+
+def test_sweep_workload_resident_full_size():
+    """The full stability-sweep workload (512 instances, fp32) advanced by one
+    resident launch per call: bitwise the per-pair launches after 10 steps,
+    and one instance of each size against its oracle run."""
+    from paper_2410_13165_amd import Batch
+    specs = inputs.sweep_specs()
+    phi0 = torch.from_numpy(inputs.sweep_phi0(specs))
+    steps = 10
+    picks = {}
+    for i, sp in enumerate(specs):
+        picks.setdefault(sp["dims"][0], i)
+    with Batch(2, specs, precision="fp32") as a, Batch(2, specs, precision="fp32") as b:
+        a.set_initial(phi0)
+        b.set_initial(phi0)
+        b.set_launch("resident")
+        a.step(steps)
+        b.step(steps)
+        for i in range(len(specs)):
+            assert torch.equal(a.instance(i).phi(), b.instance(i).phi()), i
+        offs = np.concatenate([[0], np.cumsum([int(np.prod(sp["dims"])) for sp in specs])])
+        for n, i in sorted(picks.items()):
+            sp = specs[i]
+            prob = oracle_problem(2, sp["dims"], sp["dx"], None, u=sp["u"], tau=sp["tau"],
+                                  K=sp["K"])
+            part = phi0.numpy()[offs[i]:offs[i + 1]].reshape(tuple(reversed(sp["dims"])))
+            run = O.Run(prob, phi0=to_oracle_order(part)).step(steps)
+            got = to_oracle_order(b.instance(i).phi().cpu().numpy())
+            assert rel_l2(got, run.phi()) <= 2e-5, (i, sp)
+
+
+def test_tuner_times_launch_forms_restores_state_and_caches(tmp_path, monkeypatch):
+    """lbm_batch_tune times the launches the steps use (per-pair or resident
+    form, rows per tile, single-step block shape), leaves the states where they
+    were, keeps a configuration that gives the same states as the default one,
+    and serves the same batch shape from its cache afterwards (in memory, and
+    appended to the file named by LBM_TUNE_CACHE)."""
+    from paper_2410_13165_amd import Batch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LBM_TUNE_CACHE", str(cache))
+    rng = np.random.default_rng(49)
+    specs = _specs(rng, 7, [48, 96], (0.6, 1.2), (-0.3, 0.3))
+    specs[0]["dims"] = (77, 51)  # a shape no other test tunes
+    parts, phi0 = _concat_phi0(specs, 890)
+    with Batch(2, specs, precision="fp32") as a, Batch(2, specs, precision="fp32") as b:
+        a.set_initial(phi0)
+        b.set_initial(phi0)
+        a.step(3)
+        b.step(3)
+        before = [b.instance(i).phi().clone() for i in range(len(specs))]
+        cfg = b.tune(4)
+        print("[batch] tuned", cfg, flush=True)
+        assert cfg["form"] in ("per_pair", "resident") and 8 <= cfg["ychunk"] <= 64
+        assert not cfg["cached"]
+        for i in range(len(specs)):
+            assert torch.equal(before[i], b.instance(i).phi())
+        assert b.instance(0).info()["step"] == 3
+        a.step(41)
+        b.step(41)
+        for i in range(len(specs)):
+            assert torch.equal(a.instance(i).phi(), b.instance(i).phi()), i
+        again = b.tune(4)
+        assert again["cached"] and again["form"] == cfg["form"] and again["ychunk"] == cfg["ychunk"]
+    fields = cache.read_text().split()
+    assert len(fields) == 6 and int(fields[2]) == cfg["ychunk"]
