@@ -39,7 +39,7 @@ if ROOT not in sys.path:
 
 METRIC = "D3Q19 MLUPS & % HBM peak, FP32 vs FP64 at fixed L2 error; adjoint/fwd ratio"
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_fused2_d3q19_512_fp32_traffic.md")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_fused2_d3q19_512_{mode}_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_13165_amd", "csrc", f)
                   for f in ("kernels.hip", "kernels.hpp", "fuse.hpp", "engine.hpp",
                             "lattice.hpp")]
@@ -53,12 +53,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(bytes_per_launch: float):
-    """HBM bytes per bulk launch from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken on other kernel sources."""
-    if not os.path.exists(PROFILE_TRAFFIC):
+def committed_traffic(mode: str):
+    """HBM bytes per bulk launch of one storage mode from the committed
+    rocprofv3 counter summary, or None when it is missing or was taken on
+    other kernel sources."""
+    path = PROFILE_TRAFFIC.format(mode=mode)
+    if not os.path.exists(path):
         return None
-    text = open(PROFILE_TRAFFIC).read()
+    text = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
@@ -66,10 +68,12 @@ def committed_traffic(bytes_per_launch: float):
     return float(m_val.group(1))
 
 
-def run_mode(precision: str, steps: int, warmup: int, n: int, scheme: str = "fullway", u=None):
+def run_mode(precision: str, steps: int, warmup: int, n: int, scheme: str = "fullway", u=None,
+             keep_phi: bool = False):
     """The benchmark workload in one storage mode; `scheme` / `u` switch to
     half-way walls (dx = 1/n, cell-centred nodes) and another velocity (the
-    same four cosines, seed 3)."""
+    same four cosines, seed 3).  keep_phi: also return phi at the end (a float64
+    device tensor) under "phi"."""
     import torch
     from paper_2410_13165_amd import Lattice, inputs
     w = inputs.BENCH_D3Q19
@@ -90,6 +94,7 @@ def run_mode(precision: str, steps: int, warmup: int, n: int, scheme: str = "ful
         t1 = time.perf_counter()
         prof = lat.profile_end()
         diag = lat.diagnostics()
+        phi = lat.phi().clone() if keep_phi else None
     finally:
         lat.close()
         torch.cuda.empty_cache()
@@ -123,6 +128,7 @@ def run_mode(precision: str, steps: int, warmup: int, n: int, scheme: str = "ful
         "rmse": diag["rmse"],
         "t_final": diag["t"],
         "nonfinite": diag["nonfinite"],
+        "phi": phi,
     }
 
 
@@ -140,6 +146,18 @@ def run_adjoint(precision: str = "fp32", n=None, steps=None):
     tgt = torch.from_numpy(inputs.gaussian_random_field(n, 3, w["seed_target"], w["corr"]))
     lat = Lattice(3, (n, n, n), 0.5, dx=dx, u=w["u"], precision=precision)
     try:
+        # one untimed forward + gradient first: the checkpoints and the
+        # segment states then come from the caching allocator, as in every
+        # iteration of an optimisation loop after the first
+        lat.set_initial(phi0)
+        lat.tape_begin(w["every"])
+        lat.step(steps)
+        phiN = lat.phi()
+        t_w0 = time.perf_counter()
+        lat.tape_gradient((phiN - tgt.to(phiN.device)) * dx ** 3, want_phi0=True, want_tau=True)
+        torch.cuda.synchronize()
+        cold_backward = time.perf_counter() - t_w0
+        lat.tape_end()
         lat.set_initial(phi0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -181,6 +199,7 @@ def run_adjoint(precision: str = "fp32", n=None, steps=None):
         "ratio": (t3 - t2) / fwd,
         "backward_phi0_only_s": t4 - t3,
         "ratio_phi0_only": (t4 - t3) / fwd,
+        "backward_first_call_s": cold_backward,
         "loss": loss,
         "dL_dtau": g["tau"],
         "grad_phi0_norm": gnorm,
@@ -291,6 +310,13 @@ def run_d2q9_convergence(sizes=(64, 128, 256, 512, 1024, 2048)):
               " ".join(f"{r['n']}:{r['rmse']:.3e}" + (f"({r['order']:.2f})" if r["order"] else "")
                        for r in runs), file=sys.stderr, flush=True)
         out["cases"].append({"precision": prec, "tau": tau, "runs": runs})
+    # crossover N*: the smallest grid at which a storage mode's error exceeds
+    # the float64 (discretisation) error of the same grid by 10%
+    ref = {r["n"]: r["rmse"] for r in out["cases"][0]["runs"]}
+    out["crossover_n"] = {}
+    for c in out["cases"][1:3]:
+        hit = [r["n"] for r in c["runs"] if r["rmse"] > 1.1 * ref[r["n"]]]
+        out["crossover_n"][c["precision"]] = hit[0] if hit else None
     return out
 
 
@@ -324,8 +350,8 @@ def run_sweep(steps=None, count=None, precision="fp32"):
         min_om = np.array([b.instance(i).info()["min_omega"] for i in range(len(specs))])
     taus = np.array([sp["tau"] for sp in specs])
     growth = np.sqrt(m1[:, 1] / m0[:, 1])
-    s2 = np.isclose(taus, 0.5)
     finite = np.isfinite(growth)
+    pred = sweep_prediction(specs, growth, m0[:, 3], m1[:, 3], min_om, steps)
     return {
         "workload": (f"{len(specs)} periodic D2Q9 lattices (sizes 64^2..512^2), {precision}, "
                      f"{steps} steps, tau~U(0.5,2), sigma~U(-0.75,0.75)^2, noise init"),
@@ -336,7 +362,63 @@ def run_sweep(steps=None, count=None, precision="fp32"):
         "grew_1e3": int(np.sum(~finite | (growth > 1e3))),
         "bounded": int(np.sum(finite & (growth <= 1.0 + 1e-6))),
         "entropy_stable_instances": int(np.sum(min_om > 0)),
+        "prediction": pred,
     }
+
+
+def sweep_prediction(specs, growth, ent0, ent1, min_om, steps):
+    """Per instance, the growth of ||phi|| and of the total entropy over the run
+    against what the parameters predict: the largest spectral radius of the
+    amplification matrix over the instance's wave numbers (a grid of
+    min(n, 256)^2 of them, a subset of the instance's own when n > 256),
+    computed on the GPU by lbm_stability_map, and the entropy criterion
+    min omega > 0 (Prop. 1)."""
+    import numpy as np
+    import torch
+    from paper_2410_13165_amd import lbm
+    count = len(specs)
+    rho = np.zeros(count)
+    for m in sorted({min(sp["dims"][0], 256) for sp in specs}):
+        idx = [i for i, sp in enumerate(specs) if min(sp["dims"][0], 256) == m]
+        sig = np.array([specs[i]["u"] for i in idx], dtype=np.float64)
+        s = np.array([1.0 / specs[i]["tau"] for i in idx], dtype=np.float64)
+        out = lbm.stability_map(sig, s, m=m)
+        rho[idx] = out["rho"].cpu().numpy()
+        torch.cuda.synchronize()
+    unstable = rho > 1.0 + 1e-9
+    finite = np.isfinite(growth)
+    grew = ~finite | (growth > 1.0 + 1e-6)
+    rate = np.where(finite & (growth > 0), np.log(np.where(finite & (growth > 0), growth, 1.0)) / steps,
+                    np.inf)
+    logrho = np.log(np.maximum(rho, 1e-300))
+    # growing instances: the measured rate log(growth)/steps tends to log rho
+    sel = unstable & grew & finite
+    rel_rate = np.abs(rate[sel] - logrho[sel]) / logrho[sel] if np.any(sel) else np.zeros(0)
+    ent_ratio = ent1 / ent0
+    pos = min_om > 0
+    return {
+        "predicted_unstable": int(unstable.sum()),
+        "grew": int(grew.sum()),
+        "agree": int(np.sum(unstable == grew)),
+        "unstable_not_grown": int(np.sum(unstable & ~grew)),
+        "grown_not_unstable": int(np.sum(~unstable & grew)),
+        "growth_rate_rel_err_median": float(np.median(rel_rate)) if rel_rate.size else None,
+        "growth_rate_rel_err_max": float(np.max(rel_rate)) if rel_rate.size else None,
+        "min_omega_positive": int(pos.sum()),
+        "entropy_grew_where_min_omega_positive": int(np.sum(pos & ~(ent_ratio <= 1.0 + 1e-9))),
+        "rho_max": float(np.max(rho)),
+    }
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def cpu_baseline(n_sample: int, steps: int):
@@ -358,8 +440,8 @@ def cpu_baseline(n_sample: int, steps: int):
         "cores": 1,
         "kind": "oracle",
         "sample": (f"D3Q19 full-way, {n_sample}^3 nodes at dx=1/{w['n'] - 1}, same field, "
-                   f"{steps} steps, {dt:.1f} s, numpy float64 single thread; host has "
-                   f"{os.cpu_count()} logical CPUs"),
+                   f"{steps} steps, {dt:.1f} s, numpy float64 single thread; host: "
+                   f"{cpu_model()}, {os.cpu_count()} logical CPUs"),
     }
 
 
@@ -431,15 +513,44 @@ def main(argv=None):
     # (not in counter-calibration runs, whose only large copies must be the
     # calibration copies)
     copy_gbs = measure_copy_gbs() if args.calib_copy_gib <= 0 else None
+    ceiling = None
     if copy_gbs:
-        print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+        from paper_2410_13165_amd import lbm
+        ceiling = {k: round(v, 1) for k, v in lbm.stream_ceiling().items()}
+        print(f"# device copy (torch): {copy_gbs:.0f} GB/s; float4 probes {ceiling}",
+              file=sys.stderr, flush=True)
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     results = {}
+    phis = {}
     for m in modes:
-        results[m] = run_mode(m, args.steps, args.warmup, args.n)
+        results[m] = run_mode(m, args.steps, args.warmup, args.n, keep_phi=True)
+        phis[m] = results[m].pop("phi")
         print(f"# {m}: {results[m]['mlups']:.0f} MLUPS, bulk {results[m]['bulk_gbs']:.0f} GB/s, "
               f"rmse {results[m]['rmse']:.3e}", file=sys.stderr, flush=True)
+    # per-run precision: each reduced-precision mode against the float64 run of
+    # the same workload and step count, and the discretisation error of that run
+    precision = None
+    if "fp64" in phis:
+        ref = phis["fp64"]
+        ref_norm = float(ref.norm())
+        disc = results["fp64"]["rmse"] * math.sqrt(args.n ** 3) / ref_norm
+        precision = {"steps": args.steps, "fp64_rel_discretisation_error": float(f"{disc:.4g}"),
+                     "drift_vs_fp64": {}, "below_discretisation_error": {}}
+        for m, ph in phis.items():
+            if m == "fp64":
+                continue
+            drift = float((ph - ref).norm()) / ref_norm
+            precision["drift_vs_fp64"][m] = float(f"{drift:.4g}")
+            precision["below_discretisation_error"][m] = bool(drift < disc)
+    del phis
+    torch.cuda.empty_cache()
+    for m in modes:
+        tr = committed_traffic(m)
+        r = results[m]
+        r["traffic_bytes_per_launch"] = tr
+        r["phys_gbs"] = tr / (r["bulk_ms"] / 1e3) / 1e9 if tr else None
+        r["phys_frac"] = r["phys_gbs"] / HBM_PEAK_GBS if tr else None
     head = results[modes[0]]
     fixed = None
     if not args.no_fixed_error:
@@ -475,9 +586,11 @@ def main(argv=None):
             print(f"# adjoint {name}: forward {a['forward_s']:.3f} s, backward "
                   f"{a['backward_s']:.3f} s, ratio {a['ratio']:.3f}", file=sys.stderr, flush=True)
 
-    traffic = committed_traffic(head["bulk_bytes_per_launch"]) if modes[0] == "fp32" else None
+    traffic = head["traffic_bytes_per_launch"]
+    kname = {"fp32": "k_fused2<float, false>", "fp64": "k_fused2<double, false>",
+             "fp32_split": "k_fused2_split<false>"}[modes[0]]
     if head["steps_per_launch"] == 2:
-        kernel = "k_fused2<false> (two stream-collide steps per pass, float32)"
+        kernel = f"{kname} (two stream-collide steps per pass)"
     else:
         kernel = f"k_step<3,{'float' if modes[0] != 'fp64' else 'double'}> (bulk stream-collide)"
     roofline = {
@@ -494,11 +607,16 @@ def main(argv=None):
     }
     # a plain device copy measured in the same process, for scale
     roofline["copy_gbs_measured"] = round(copy_gbs, 1) if copy_gbs else None
+    roofline["stream_ceiling_gbs"] = ceiling
     if traffic:
-        # measured HBM bytes per launch over the same duration
-        roofline["hbm_gbs_measured"] = round(traffic / (head["bulk_ms"] / 1e3) / 1e9, 1)
-        if copy_gbs:
-            roofline["hbm_frac_of_copy"] = round(roofline["hbm_gbs_measured"] / copy_gbs, 4)
+        # measured HBM bytes per launch (committed counters) over the same
+        # duration: the physical rate, against the peak and the float4 copy
+        roofline["hbm_gbs_measured"] = round(head["phys_gbs"], 1)
+        roofline["phys_frac"] = round(head["phys_frac"], 4)
+        if ceiling:
+            roofline["phys_frac_of_copy_ceiling"] = round(head["phys_gbs"] / ceiling["copy"], 4)
+    else:
+        roofline["phys_frac"] = None
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_nodes, args.cpu_steps)
@@ -528,6 +646,10 @@ def main(argv=None):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "hbm_frac_step": round(head["hbm_frac_step"], 4),
+        "value_fp32_split": round(results["fp32_split"]["mlups"], 1) if "fp32_split" in results
+        else None,
+        "value_fp64": round(results["fp64"]["mlups"], 1) if "fp64" in results else None,
+        "precision": precision,
         "modes": {m: {k: (float(f"{v:.6g}") if isinstance(v, float) else v)
                       for k, v in r.items()}
                   for m, r in results.items()},

@@ -392,6 +392,20 @@ int lbm_batch_moments(lbm_batch* b, double* scalars_host);
 const char* lbm_batch_last_error(const lbm_batch* b);
 int lbm_batch_destroy(lbm_batch* b);
 
+/* Streaming probe of the device memory (no lattice): the bandwidth a plain
+   float4 grid-stride stream reaches, the denominator of the fraction of what
+   the memory system delivers (beside the nominal peak).  kind 0: copy src to
+   dst (bytes read + bytes written count); 1: read src (dst receives one float
+   per block, so it holds at least 4 * blocks bytes); 2: write dst with
+   non-temporal stores.  bytes: the array size, a multiple of 16; blocks of 256
+   threads, 1..2^20; iters timed launches after one warm-up, on `stream`
+   (hipStream_t, NULL = default), synchronising it.  *gbs_out = bytes moved per
+   launch x iters / elapsed.  Errors: LBM_EINVAL for arguments out of range,
+   LBM_EDEVICE for a failed launch; lbm_probe_last_error() gives the message. */
+int lbm_bandwidth_probe(int kind, void* dst_dev, const void* src_dev, int64_t bytes, int blocks,
+                        int iters, void* stream, double* gbs_out);
+const char* lbm_probe_last_error(void);
+
 const char* lbm_last_error(const lbm_handle* h);
 
 /* Release all device memory of h (through free_fn).  NULL is accepted. */

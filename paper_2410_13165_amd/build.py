@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
 SOURCES = ["kernels.hip", "walls_d1.hip", "walls_d2.hip", "walls_d3.hip", "walls_d3t.hip",
            "walls_d4.hip", "walls_d4t.hip",
-           "adjoint.hip", "stability.hip", "capi.hip"]
+           "adjoint.hip", "stability.hip", "probe.hip", "capi.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -104,6 +104,9 @@ SIGNATURES = {
     "lbm_batch_destroy": (C.c_int, [C.c_void_p]),
     "lbm_stability_map": (C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_double,
                                     C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lbm_bandwidth_probe": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
+                                      C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
+    "lbm_probe_last_error": (C.c_char_p, []),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_destroy": (C.c_int, [C.c_void_p]),
 }
@@ -177,6 +180,33 @@ def stability_map(sigma, s, m: int = 32, g: float = 0.5, device: str = "cuda"):
     if rc != OK:
         raise LbmError(rc, lib.lbm_last_error(None).decode())
     return {"rho": rho, "min_omega": mw, "unconverged": unc}
+
+
+def stream_ceiling(gib: float = 4.0, blocks=(1024, 4096, 16384, 65536), iters: int = 10,
+                   device: str = "cuda") -> dict:
+    """Best bandwidth (GB/s) of the library's float4 copy, read and write
+    probes over `gib` GiB arrays and the given grid sizes."""
+    import torch
+    lib = load_library()
+    nbytes = int(gib * (1 << 30)) // 16 * 16
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=device)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream(a.device).cuda_stream
+    out = {}
+    for kind, name in ((0, "copy"), (1, "read"), (2, "write")):
+        best = 0.0
+        for nb in blocks:
+            g = C.c_double()
+            rc = lib.lbm_bandwidth_probe(kind, C.c_void_p(b.data_ptr()), C.c_void_p(a.data_ptr()),
+                                         nbytes, int(nb), int(iters), C.c_void_p(stream),
+                                         C.byref(g))
+            if rc != OK:
+                raise LbmError(rc, lib.lbm_probe_last_error().decode())
+            best = max(best, g.value)
+        out[name] = best
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 class LbmError(RuntimeError):
