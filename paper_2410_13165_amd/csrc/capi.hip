@@ -922,9 +922,9 @@ int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0
     cleanup();
     return fail(h, LBM_ENOMEM, "adjoint buffers");
   }
-  hipError_t e = hipMemsetAsync(lam[0], 0, pb, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(lam[1], 0, pb, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(partial, 0, sizeof(double) * npart, h->stream);
+  // lam[0] is written for every node by the seed and lam[1] by the first
+  // adjoint step; the slots past the nodes are never read
+  hipError_t e = hipMemsetAsync(partial, 0, sizeof(double) * npart, h->stream);
   if (e == hipSuccess && want_wall)
     e = hipMemsetAsync(partial_wall, 0, sizeof(double) * wall_grad_partials(), h->stream);
   if (e == hipSuccess) e = launch_adjoint_seed(kp, h->precision, dl_dphi_dev, lam[0], h->stream);

@@ -14,9 +14,18 @@
 // k_step_split, k_wall_split
 //              the same step on the (phi float64, g = f - omega phi float32)
 //              representation.
+// k_fused2, k_fused2_split, k_fused2_d2
+//              two time steps per pass (d = 3 any storage, d = 2 float32 and
+//              float64), the intermediate state in LDS; bitwise two k_step.
+// k_step_batch, k_fused2_d2_batch, k_fused2_d2_resident
+//              many periodic lattices in one launch per step, per pair of
+//              steps, or (resident) per call with one block per instance.
 // k_init       initial state of order K = 1 or 3 (eq. ini-simp).
 // k_moments    phi, RMSE (eq. rmse), total microscopic entropy (eq. skfk) and
-//              safety statistics as deterministic float64 reductions.
+//              safety statistics as deterministic float64 reductions, the
+//              work selected by the caller's mask.
+// k_count_nonfinite
+//              the periodic non-finite check of lbm_step.
 //
 // Memory layout: structure of arrays, population k of node `node` at
 // base[k * pstride + node], nodes ordered with x_1 fastest.  A block covers
