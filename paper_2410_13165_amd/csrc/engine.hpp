@@ -53,6 +53,7 @@ struct KParams {
   signed char cv[kMaxQ][kMaxDim];  // velocities (Sec. 2.3 order)
   int kbar[kMaxQ];                 // c_kbar = -c_k
   double s, tau, dt, dx, R;
+  double dtR;              // dt R, the source term of one step (split mode)
   float s_f;
   double origin[kMaxDim];
   double shift[kMaxDim];   // 1/2 on half-way axes, else 0

@@ -196,7 +196,7 @@ static hipError_t fused_pair_split(const KParams& p, const FusedBufs& fb, long l
                                    hipStream_t stream, hipEvent_t* ev) {
   using S = FuseSplitShape<HALF>;
   constexpr int R = (S::TX + 2) * (S::TY + 2);
-  constexpr size_t lds = sizeof(float) * S::SLOTS * R + sizeof(double) * 3 * R;
+  constexpr size_t lds = fuse_split_lds<HALF>();
   static_assert(lds <= 160 * 1024, "fused tile exceeds the LDS of a CU");
   static_assert((sizeof(float) * S::SLOTS * R) % 8 == 0, "phi planes must be 8-byte aligned");
   static bool attr_set = false;

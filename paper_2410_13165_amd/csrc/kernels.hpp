@@ -922,11 +922,19 @@ __global__ void __launch_bounds__(256)
 // Split representation: phi (float64) and g_k = f_k - omega_k phi (float32),
 // pre-collision.  f*_k(y) = omega_k (phi(y) + dt R) + (1 - s) g_k(y), so the
 // pull needs phi and g_k at the upwind node only; arithmetic is float64.
-// Every kernel of the mode evaluates f* with split_fstar_val (two-step passes
-// equal single steps bit for bit), with one uniform constant per population.
+// Every kernel of the mode evaluates f* from t = split_src(phi) with
+// split_fstar_t (two-step passes equal single steps bit for bit); the passes
+// that keep phi of a plane in LDS keep t, formed once per node.
+__device__ __forceinline__ double split_src(double phi, const KParams& p) { return phi + p.dtR; }
+
+__device__ __forceinline__ double split_fstar_t(double omega, double t, float g,
+                                                const KParams& p) {
+  return fma(omega, t, (1.0 - p.s) * static_cast<double>(g));
+}
+
 __device__ __forceinline__ double split_fstar_val(double omega, double phi, float g,
                                                   const KParams& p) {
-  return fma(omega, phi + p.dt * p.R, (1.0 - p.s) * static_cast<double>(g));
+  return split_fstar_t(omega, split_src(phi, p), g, p);
 }
 
 template <int D>
@@ -998,20 +1006,36 @@ __global__ void __launch_bounds__(256)
 }
 
 // Two fused steps of the split representation (d = 3), organised as k_fused2:
-// the LDS keeps the step-1 g_k (float32, the same plane slots) and phi
-// (float64, a ring of three planes).  The x_1-face data of step 2 come from a
-// second x-face array (xd2); rows on and next to the walls of x_2 / x_3 go
-// through the scratch state (gC, phiC) as in k_fused2.
+// the LDS keeps the step-1 g_k (float32, the same plane slots) and
+// t = split_src(phi) (float64, a ring of three planes).  The x_1-face data of
+// step 2 come from a second x-face array (xd2); rows on and next to the walls
+// of x_2 / x_3 go through the scratch state (gC, phiC) as in k_fused2.
+//
+// Step 1 pulls phi from the 19 upwind nodes of every node of its region.  A
+// third ring of three planes holds t of the source phi over the region and a
+// halo of one more node, (TX + 4)(TY + 4) values per plane, loaded once per
+// plane.  Gathered from global memory instead, every source plane is read 19
+// times per node over three iterations, more than the L2 of an XCD holds
+// (measured: 1.67x the algorithmic reads of the pass, 1.17x with the ring).
 template <bool HALF>
 struct FuseSplitShape;
 template <>
 struct FuseSplitShape<false> {
-  static constexpr int TX = 64, TY = 11, NT = 512, SLOTS = 38;
+  static constexpr int TX = 64, TY = 10, NT = 1024, SLOTS = 38;
 };
 template <>
 struct FuseSplitShape<true> {
-  static constexpr int TX = 64, TY = 10, NT = 512, SLOTS = 43;
+  static constexpr int TX = 64, TY = 9, NT = 1024, SLOTS = 43;
 };
+
+// bytes of LDS of a split pass: g slots, the step-1 phi ring, the source phi ring
+template <bool HALF>
+constexpr size_t fuse_split_lds() {
+  using S = FuseSplitShape<HALF>;
+  return sizeof(float) * S::SLOTS * (S::TX + 2) * (S::TY + 2) +
+         sizeof(double) * 3 * (S::TX + 2) * (S::TY + 2) +
+         sizeof(double) * 3 * (S::TX + 4) * (S::TY + 4);
+}
 
 template <bool HALF>
 __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
@@ -1022,10 +1046,12 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
   using S = FuseSplitShape<HALF>;
   constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
   constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
+  constexpr int PX = TX + 4, PY = TY + 4, P2 = PX * PY;
   constexpr int SX = 2 * D - 1;
   extern __shared__ __align__(16) unsigned char fuse_lds[];
   float* lg = reinterpret_cast<float*>(fuse_lds);
   double* lphi = reinterpret_cast<double*>(fuse_lds + sizeof(float) * S::SLOTS * R);
+  double* lsrc = lphi + 3 * R;
   const long long ps = p.pstride;
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
   int tx_, ty_, tz_;
@@ -1033,6 +1059,35 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
   const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * zc;
   const int zend = min(zc0 + zc, n2);
   const int iters = zend - zc0 + 2;
+  // t of the source phi of plane z (zc0 - 2 <= z <= zend + 1) into ring slot
+  // (z - zc0 + 2) mod 3, at (x_1, x_2) = (x0 - 2 + sx, y0 - 2 + sy).  Positions
+  // outside a Dirichlet axis stay unwritten: they are read only by pulls that
+  // the x_1-face data replace (rows on the walls of x_2 / x_3 pull nothing).
+  auto stage = [&](int z) {
+    int gz = z;
+    if (gz < 0 || gz >= n2) {
+      if (p.bc[2] != 0) return;
+      gz = fuse_wrap(gz, n2);
+    }
+    double* dst = lsrc + ((z - zc0 + 2) % 3) * P2;
+    for (int t = threadIdx.x; t < P2; t += NT) {
+      const int sx = t % PX, sy = t / PX;
+      int gx = x0 - 2 + sx, gy = y0 - 2 + sy;
+      if (gx < 0 || gx >= n0) {
+        if (p.bc[0] != 0) continue;
+        gx = fuse_wrap(gx, n0);
+      }
+      if (gy < 0 || gy >= n1) {
+        if (p.bc[1] != 0) continue;
+        gy = fuse_wrap(gy, n1);
+      }
+      dst[t] = split_src(phiA[(static_cast<long long>(gz) * n1 + gy) * n0 + gx], p);
+    }
+  };
+  stage(zc0 - 2);
+  stage(zc0 - 1);
+  stage(zc0);
+  __syncthreads();
   for (int it = 0; it < iters; ++it) {
     const int zp = zc0 - 1 + it;
     // plain region order: with two items per thread the halo-column items of
@@ -1067,8 +1122,18 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
           g[k] = gC[k * ps + node];
         });
       } else {
+        // split_pull with phi from the source ring: plane zp - c_3 is in
+        // slot (it + 1 - c_3) mod 3
+        const int sown = (ry + 1) * PX + rx + 1;
+        const double* s0 = lsrc + ((it + 1) % 3) * P2 + sown;
         double f[Q];
-        split_pull<D>(f, gA, phiA, ps, node, ri, p);
+        static_for<0, Q>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          constexpr Vec4i c = vel_vec(D, k);
+          const double* sp = c.v[2] == 0 ? s0 : lsrc + ((it + 1 - c.v[2]) % 3) * P2 + sown;
+          const double ph = sp[-c.v[1] * PX - c.v[0]];
+          f[k] = split_fstar_t(p.omega[k], ph, gA[k * ps + node + pull_offset<D, k>(ri)], p);
+        });
         if (ri.lo[0] || ri.hi[0]) {
           const double* W = p.xdata + (ri.hi[0] ? SX * p.rows : 0) + row;
           static_for<0, Q>([&](auto K) {
@@ -1077,7 +1142,10 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
             if constexpr (cx != 0) {
               if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
                 double v = W[(long long)xface_slot(D, k) * p.rows];
-                if (HALF) v -= split_fstar<D>(gA, phiA, ps, node, opp_index(D, k), p);
+                if (HALF) {
+                  constexpr int kb = opp_index(D, k);
+                  v -= split_fstar_t(p.omega[kb], *s0, gA[kb * ps + node], p);
+                }
                 f[k] = v;
               }
             }
@@ -1103,7 +1171,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
         constexpr int k = decltype(K)::value;
         lg[fuse_slot<HALF, k>(it) * R + r] = g[k];
       });
-      lphi[(it % 3) * R + r] = phi;
+      lphi[(it % 3) * R + r] = split_src(phi, p);
     }
     __syncthreads();
     if (it >= 2) {
@@ -1126,7 +1194,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
           const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
           const double ph = lphi[((it - src_it) % 3) * R + rr];
           const float gk = lg[fuse_slot<HALF, k>(it - src_it) * R + rr];
-          f[k] = split_fstar_val(p.omega[k], ph, gk, p);
+          f[k] = split_fstar_t(p.omega[k], ph, gk, p);
         });
         if (ri.lo[0] || ri.hi[0]) {
           const double* W = xd2 + (ri.hi[0] ? SX * p.rows : 0) + row;
@@ -1141,7 +1209,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
                   constexpr int kb = opp_index(D, k);
                   const double ph = lphi[((it - 1) % 3) * R + own];
                   const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
-                  v -= split_fstar_val(p.omega[kb], ph, gb, p);
+                  v -= split_fstar_t(p.omega[kb], ph, gb, p);
                 }
                 f[k] = v;
               }
@@ -1151,6 +1219,9 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
         split_store<D>(f, gB, phiB, ps, node, p);
       }
     }
+    // the next iteration's source plane zp + 2 replaces plane zp - 1, which
+    // this iteration's step 1 was the last to read
+    if (it + 1 < iters) stage(zp + 2);
     __syncthreads();
   }
 }
