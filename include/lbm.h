@@ -63,7 +63,12 @@ typedef enum {
   LBM_ENONFINITE = -5     /* non-finite values detected (lbm_params.check_every) */
 } lbm_status;
 
-/* Boundary condition of one axis (both faces of the axis take the same kind). */
+/* Boundary kind of one face (lbm_params.bc[axis][side]).  The two faces of an
+   axis are both periodic or both Dirichlet (LBM_EINVAL otherwise), and every
+   Dirichlet face of a lattice uses the same scheme: a lattice that mixes
+   full-way and half-way faces, on one axis or on two, is LBM_EUNSUPPORTED
+   (Sec. 3.2 defines the two schemes; a population entering through faces of
+   both kinds at an edge would need a rule the paper does not give). */
 typedef enum {
   LBM_BC_PERIODIC = 0,    /* periodic wrap, nodes at origin + i dx                       */
   LBM_BC_FULLWAY = 1,     /* wall on the nodes i = 0 and i = N-1 (Fig. 1, full-way case)  */
@@ -122,8 +127,8 @@ typedef struct {
   double g;                     /* interpolation weight of eq. (meq-4rd), default 1/2 */
   double m4;                    /* explicit fourth-order moment when use_m4 != 0      */
   int32_t use_m4;
-  int32_t bc[LBM_MAX_DIM];      /* lbm_bc per axis; full-way and half-way axes may
-                                   not be mixed in one lattice                        */
+  int32_t bc[LBM_MAX_DIM][2];   /* lbm_bc of the lower [a][0] and upper [a][1] face
+                                   of axis a (see lbm_bc for the combinations)        */
   int32_t bc_order;             /* P: full-way {1,3,4}, half-way {1,2,3,4}; default 4 */
   int32_t init_order;           /* K in {1,3}; default 3                              */
   int32_t precision;            /* lbm_precision; default LBM_FP64                    */
@@ -175,9 +180,10 @@ void lbm_params_default(lbm_params* p);
    when p->field is given, writes the initial state of order p->init_order
    (eq. ini-simp) from the analytic field.  Parameters outside the entropy-stability
    region are accepted; lbm_info reports min_omega and entropy_stable.
-   Errors: LBM_EINVAL (d, dims, tau, dx, orders, bc codes, a Dirichlet axis without
-   a field, fewer than 2 nodes on a Dirichlet axis, more than 2^31-1 nodes),
-   LBM_EUNSUPPORTED (mixed full-way/half-way axes, a tanh field with walls),
+   Errors: LBM_EINVAL (d, dims, tau, dx, orders, bc codes, a periodic face opposite
+   a Dirichlet face, a Dirichlet axis without a field, fewer than 2 nodes on a
+   Dirichlet axis, more than 2^31-1 nodes), LBM_EUNSUPPORTED (full-way and
+   half-way faces in one lattice, a tanh field with walls),
    LBM_ENOMEM, LBM_EDEVICE.  On failure *out is NULL. */
 int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p,
                lbm_handle** out);

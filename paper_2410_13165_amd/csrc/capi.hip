@@ -335,15 +335,21 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
     nodes *= dims[a];
     if (nodes > std::numeric_limits<int32_t>::max())
       return fail(nullptr, LBM_EINVAL, "more than 2^31-1 nodes");
-    const int bc = p->bc[a];
-    if (bc != LBM_BC_PERIODIC && bc != LBM_BC_FULLWAY && bc != LBM_BC_HALFWAY)
-      return fail(nullptr, LBM_EINVAL, "unknown boundary code");
-    if (bc != LBM_BC_PERIODIC) {
+    const int lo = p->bc[a][0], hi = p->bc[a][1];
+    for (const int bc : {lo, hi})
+      if (bc != LBM_BC_PERIODIC && bc != LBM_BC_FULLWAY && bc != LBM_BC_HALFWAY)
+        return fail(nullptr, LBM_EINVAL, "unknown boundary code");
+    if ((lo == LBM_BC_PERIODIC) != (hi == LBM_BC_PERIODIC))
+      return fail(nullptr, LBM_EINVAL, "a periodic face needs a periodic opposite face");
+    if (lo != LBM_BC_PERIODIC) {
       if (dims[a] < 2) return fail(nullptr, LBM_EINVAL, "a Dirichlet axis needs >= 2 nodes");
-      const int sch = bc == LBM_BC_FULLWAY ? kFullWay : kHalfWay;
-      if (scheme != kNoWall && scheme != sch)
-        return fail(nullptr, LBM_EUNSUPPORTED, "full-way and half-way axes cannot be mixed");
-      scheme = sch;
+      for (const int bc : {lo, hi}) {
+        const int sch = bc == LBM_BC_FULLWAY ? kFullWay : kHalfWay;
+        if (scheme != kNoWall && scheme != sch)
+          return fail(nullptr, LBM_EUNSUPPORTED,
+                      "full-way and half-way faces cannot be mixed in one lattice");
+        scheme = sch;
+      }
     }
   }
   if (scheme == kFullWay && p->bc_order != 1 && p->bc_order != 3 && p->bc_order != 4)
@@ -361,7 +367,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   if (p->check_every < 0) return fail(nullptr, LBM_EINVAL, "check_every must be >= 0");
   if (p->wall_data == LBM_WALL_TANGENTIAL)
     for (int a = 0; a < d; ++a)
-      if (p->bc[a] != LBM_BC_PERIODIC && !(std::fabs(p->u[a]) > 0.0))
+      if (p->bc[a][0] != LBM_BC_PERIODIC && !(std::fabs(p->u[a]) > 0.0))
         return fail(nullptr, LBM_EINVAL,
                     "tangential wall data need u_j != 0 on every Dirichlet axis j");
 
@@ -397,11 +403,11 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
     kp.n[a] = static_cast<int>(n);
     kp.stride[a] = static_cast<int>(st);
     st *= n;
-    kp.bc[a] = a < d ? p->bc[a] : 0;
+    kp.bc[a] = a < d ? p->bc[a][0] : 0;
     kp.origin[a] = a < d ? p->origin[a] : 0.0;
     kp.u[a] = a < d ? p->u[a] : 0.0;
-    kp.inv_u[a] = (a < d && p->bc[a] != LBM_BC_PERIODIC && p->u[a] != 0.0) ? 1.0 / p->u[a] : 0.0;
-    kp.shift[a] = (a < d && p->bc[a] == LBM_BC_HALFWAY) ? 0.5 : 0.0;
+    kp.inv_u[a] = (a < d && p->bc[a][0] != LBM_BC_PERIODIC && p->u[a] != 0.0) ? 1.0 / p->u[a] : 0.0;
+    kp.shift[a] = (a < d && p->bc[a][0] == LBM_BC_HALFWAY) ? 0.5 : 0.0;
   }
   kp.wall_data = p->wall_data;
   kp.nodes = static_cast<int>(nodes);
@@ -409,7 +415,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   // population planes: the nodes, then (with walls on x_1) one slot per row
   // for the x_1-face wall data; 256-byte aligned
   kp.xoff = static_cast<int>(nodes);
-  const int64_t plane = nodes + (p->bc[0] != LBM_BC_PERIODIC ? nodes / dims[0] : 0);
+  const int64_t plane = nodes + (p->bc[0][0] != LBM_BC_PERIODIC ? nodes / dims[0] : 0);
   if (plane > std::numeric_limits<int32_t>::max()) {
     delete h;
     return fail(nullptr, LBM_EINVAL, "more than 2^31-1 nodes plus wall slots");
@@ -1373,7 +1379,7 @@ int lbm_batch_create(int count, int d, const int64_t* dims, const double* tau,
     if (params[i].precision == LBM_FP32_SPLIT)
       return abort_create(bfail(nullptr, LBM_EUNSUPPORTED, "batches support LBM_FP64 and LBM_FP32"));
     for (int a = 0; a < d; ++a)
-      if (params[i].bc[a] != LBM_BC_PERIODIC)
+      if (params[i].bc[a][0] != LBM_BC_PERIODIC || params[i].bc[a][1] != LBM_BC_PERIODIC)
         return abort_create(bfail(nullptr, LBM_EUNSUPPORTED, "batch instances must be periodic"));
     lbm_handle* h = nullptr;
     int rc = lbm_create(d, dims + static_cast<size_t>(i) * d, tau[i], &params[i], &h);

@@ -48,7 +48,7 @@ class LbmParams(C.Structure):
         ("struct_size", C.c_uint32),
         ("dx", C.c_double), ("origin", C.c_double * MAX_DIM), ("u", C.c_double * MAX_DIM),
         ("R", C.c_double), ("g", C.c_double), ("m4", C.c_double), ("use_m4", C.c_int32),
-        ("bc", C.c_int32 * MAX_DIM), ("bc_order", C.c_int32), ("init_order", C.c_int32),
+        ("bc", (C.c_int32 * 2) * MAX_DIM), ("bc_order", C.c_int32), ("init_order", C.c_int32),
         ("precision", C.c_int32), ("field", C.POINTER(LbmField)),
         ("alloc", _ALLOC), ("free_fn", _FREE), ("alloc_ctx", C.c_void_p),
         ("stream", C.c_void_p), ("wall_data", C.c_int32), ("steps_per_pass", C.c_int32),
@@ -236,12 +236,13 @@ class Field:
 class Lattice:
     """One lattice of the fourth-order BGK model on the current CUDA/HIP device.
 
-    dims = (N_1, ..., N_d); bc = one of "periodic", "fullway", "halfway" per axis.
+    dims = (N_1, ..., N_d); bc[a] = "periodic", "fullway" or "halfway" for both
+    faces of axis a, or a pair (lower face, upper face) of them.
     """
 
     def __init__(self, d: int, dims: Sequence[int], tau: float = 0.5, *, dx: float,
                  u: Sequence[float], R: float = 0.0, origin: Optional[Sequence[float]] = None,
-                 bc: Optional[Sequence[str]] = None, P: int = 4, K: int = 3,
+                 bc: Optional[Sequence] = None, P: int = 4, K: int = 3,
                  precision: str = "fp64", field=None, g: float = 0.5,
                  m4: Optional[float] = None, wall_data: str = "jets",
                  steps_per_pass: int = 2, check_every: int = 0, device=None):
@@ -263,7 +264,9 @@ class Lattice:
         for a in range(self.d):
             p.origin[a] = float(origin[a]) if origin is not None else 0.0
             p.u[a] = float(u[a])
-            p.bc[a] = BC[bc[a]] if bc is not None else 0
+            faces = bc[a] if bc is not None else "periodic"
+            lo, hi = (faces, faces) if isinstance(faces, str) else faces
+            p.bc[a][0], p.bc[a][1] = BC[lo], BC[hi]
         p.R = float(R)
         p.g = float(g)
         if m4 is not None:

@@ -29,7 +29,7 @@ def oracle_problem(d, dims, dx, spec=None, u=None, R=None, tau=0.5, bc=None, P=4
     u = spec["u"] if u is None else u
     R = spec.get("R", 0.0) if (R is None and spec is not None) else (R or 0.0)
     if faces is None:
-        faces = [(b, b) for b in (bc or ["periodic"] * d)]
+        faces = [(b, b) if isinstance(b, str) else tuple(b) for b in (bc or ["periodic"] * d)]
     return O.Problem(d, dims, dx, u, R=R, tau=tau, origin=origin, bc=faces, P=P, K=K,
                      field=oracle_field(spec, d), shift=shift, wall_data=wall_data)
 

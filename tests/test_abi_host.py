@@ -88,7 +88,7 @@ def test_params_default():
     lib.lbm_params_default(C.byref(p))
     assert p.struct_size == C.sizeof(B.LbmParams)
     assert p.dx == 1.0 and p.g == 0.5 and p.bc_order == 4 and p.init_order == 3
-    assert p.precision == 0 and list(p.bc) == [0, 0, 0, 0]
+    assert p.precision == 0 and [list(b) for b in p.bc] == [[0, 0]] * 4
     assert p.wall_data == 0 and p.steps_per_pass == 2 and p.check_every == 0
 
 
@@ -98,8 +98,10 @@ def _create(d, dims, tau, **kw):
     lib.lbm_params_default(C.byref(p))
     for k, v in kw.items():
         if k == "bc":
+            # per axis: one code for both faces, or a (lower, upper) pair
             for a, b in enumerate(v):
-                p.bc[a] = b
+                lo, hi = (b, b) if isinstance(b, int) else b
+                p.bc[a][0], p.bc[a][1] = lo, hi
         else:
             setattr(p, k, v)
     arr = (C.c_int64 * 4)(*(list(dims) + [1] * (4 - len(dims))))
@@ -126,6 +128,16 @@ def test_create_rejects_walls_without_field_and_mixed_schemes():
     assert rc == B.EINVAL and "field" in err
     rc, h, err = _create(2, (8, 8), 0.5, bc=[1, 2])
     assert rc == B.EUNSUPPORTED and "mixed" in err
+    # per-face codes: a periodic face needs a periodic opposite face, and the
+    # faces of one axis cannot mix the two schemes either
+    rc, h, err = _create(2, (8, 8), 0.5, bc=[(0, 1), 0])
+    assert rc == B.EINVAL and "periodic face" in err
+    rc, h, err = _create(2, (8, 8), 0.5, bc=[0, (2, 0)])
+    assert rc == B.EINVAL and "periodic face" in err
+    rc, h, err = _create(2, (8, 8), 0.5, bc=[(1, 2), 0])
+    assert rc == B.EUNSUPPORTED and "mixed" in err
+    rc, h, err = _create(2, (8, 8), 0.5, bc=[(1, 3), 0])
+    assert rc == B.EINVAL and "boundary code" in err
     rc, h, err = _create(2, (1, 8), 0.5, bc=[1, 0])
     assert rc == B.EINVAL and "2 nodes" in err
     rc, h, err = _create(2, (8, 8), 0.5, init_order=2)
@@ -147,7 +159,7 @@ def test_tangential_wall_data_needs_nonzero_normal_velocity():
     f = B.LbmField()
     f.kind, f.n_modes, f.amps, f.kvecs = 1, 1, amps, kv
     p.field = C.pointer(f)
-    p.bc[0], p.bc[1] = 0, 1
+    p.bc[1][0] = p.bc[1][1] = 1
     p.u[0], p.u[1] = 0.1, 0.0
     p.wall_data = 1
     arr = (C.c_int64 * 4)(8, 8, 1, 1)

@@ -93,6 +93,9 @@ def test_mixed_periodic_and_dirichlet_axes(scheme):
     spec = inputs.random_cosines(3, [0.05, -0.1, 0.08], 0.5, seed=31, kmax=1.0)
     _check_pair(3, (40, 18, 21), 1.0 / 39, spec, 12, bc=["periodic", scheme, scheme])
     _check_pair(3, (40, 18, 21), 1.0 / 39, spec, 12, bc=[scheme, "periodic", scheme])
+    # the same lattices with the faces given one by one (lbm_params.bc[a][side])
+    _check_pair(3, (40, 18, 21), 1.0 / 39, spec, 12,
+                bc=[(scheme, scheme), ("periodic", "periodic"), (scheme, scheme)])
 
 
 @pytest.mark.parametrize("scheme", ["fullway", "halfway"])
