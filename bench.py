@@ -6,8 +6,9 @@ walls on all six faces (data from four random cosines, seed 3),
 u = (0.05, 0.1, 0.08), R = 1, tau = 1/2, third-order initialisation, fourth-order
 walls.  One step is one time step of the whole lattice (bulk kernel + wall
 kernel); `value` is the float32-storage throughput in million lattice updates
-per second with all state resident in HBM.  The float64 and float32-split
-storage modes are measured on the same workload for the precision comparison.
+per second with all state resident in HBM.  The float64, float32-split
+(float64 phi) and hi/lo (float32 arithmetic, phi as a float32 pair) storage
+modes are measured on the same workload for the precision comparison.
 
 The roofline entry is for the dominant kernel (the bulk stream-collide; in
 float32 it advances two time steps per launch, keeping the intermediate state
@@ -105,8 +106,8 @@ def run_mode(precision: str, steps: int, warmup: int, n: int, scheme: str = "ful
     bulk_nodes = (n - 2) ** 2 * n
     q = info["q"]
     esize = 8 if precision == "fp64" else 4
-    bulk_bytes_step = bulk_nodes * 2 * q * esize + (bulk_nodes * 16 if precision == "fp32_split"
-                                                     else 0)
+    bulk_bytes_step = bulk_nodes * 2 * q * esize + (
+        bulk_nodes * 16 if precision in ("fp32_split", "fp32_hilo") else 0)
     # a bulk launch covers steps_per_launch time steps (two when the lattice
     # advances in fused pairs); its algorithmic bytes are those of its steps
     steps_per_launch = prof["steps"] / prof["launches"]
@@ -217,7 +218,7 @@ def run_fixed_error(target=1e-6, sizes=(64, 96, 128, 192, 256, 384, 512)):
     T = w["steps"] / (w["n"] - 1)
     spec = inputs.bench_field()
     out = {}
-    for mode in ("fp64", "fp32_split", "fp32"):
+    for mode in ("fp64", "fp32_split", "fp32_hilo", "fp32"):
         tried = []
         hit = None
         for n in sizes:
@@ -472,7 +473,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512, help="nodes per axis")
-    ap.add_argument("--modes", default="fp32,fp64,fp32_split",
+    ap.add_argument("--modes", default="fp32,fp64,fp32_split,fp32_hilo",
                     help="storage modes; the first one gives `value`")
     ap.add_argument("--cpu-nodes", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=60)
@@ -588,7 +589,8 @@ def main(argv=None):
 
     traffic = head["traffic_bytes_per_launch"]
     kname = {"fp32": "k_fused2<float, false>", "fp64": "k_fused2<double, false>",
-             "fp32_split": "k_fused2_split<false>"}[modes[0]]
+             "fp32_split": "k_fused2_split<false, false>",
+             "fp32_hilo": "k_fused2_split<false, true>"}[modes[0]]
     if head["steps_per_launch"] == 2:
         kernel = f"{kname} (two stream-collide steps per pass)"
     else:
@@ -621,7 +623,7 @@ def main(argv=None):
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_nodes, args.cpu_steps)
 
-    dtype = {"fp32": "f32", "fp64": "f64", "fp32_split": "f32+f64"}[modes[0]]
+    dtype = {"fp32": "f32", "fp64": "f64", "fp32_split": "f32+f64", "fp32_hilo": "f32"}[modes[0]]
     line = {
         "metric": METRIC,
         "value": round(head["mlups"], 1),
@@ -647,6 +649,8 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "hbm_frac_step": round(head["hbm_frac_step"], 4),
         "value_fp32_split": round(results["fp32_split"]["mlups"], 1) if "fp32_split" in results
+        else None,
+        "value_fp32_hilo": round(results["fp32_hilo"]["mlups"], 1) if "fp32_hilo" in results
         else None,
         "value_fp64": round(results["fp64"]["mlups"], 1) if "fp64" in results else None,
         "precision": precision,

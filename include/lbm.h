@@ -81,8 +81,17 @@ typedef enum {
   LBM_FP32 = 1,           /* post-collision populations in float32 as deviations from the
                              uniform exact state omega_k (phi_mean + R t), float32
                              arithmetic with compensated sums                            */
-  LBM_FP32_SPLIT = 2      /* phi in float64 plus g_k = f_k - omega_k phi in float32,
+  LBM_FP32_SPLIT = 2,     /* phi in float64 plus g_k = f_k - omega_k phi in float32,
                              float64 arithmetic                                          */
+  LBM_FP32_HILO = 3       /* g_k as in LBM_FP32_SPLIT, phi as an unevaluated pair
+                             hi + lo of float32 (the same 8 bytes per node), float32
+                             arithmetic: each population enters as its offset
+                             b_k = f_k - omega_k (phi(x) + dt R) from the node's own
+                             phi, with phi(x - c_k) - phi(x) = (hi' - hi) + (lo' - lo);
+                             the new phi = phi(x) + dt R + sum_k b_k with dt R an
+                             exact float32 pair, by error-free sums (values a wall
+                             scheme sets, and rows on the walls of x_2 .. x_d, use
+                             float64).  No tapes or batches.                     */
 } lbm_precision;
 
 /* Analytic solution family phi*(x, t) = F(x - u t) + R t used for the analytic
@@ -308,7 +317,8 @@ int lbm_profile_end(lbm_handle* h, double* bulk_ms, double* wall_ms, int64_t* st
    Errors: LBM_EINVAL (no tape, a tape that does not cover the current step,
    NULL dl_dphi, phi0 outputs without an initial tape, dl_dwall without
    Dirichlet walls or without a cos/exp field), LBM_EUNSUPPORTED (dL/dtau at
-   s = 1 with post-collision storage), LBM_ENOMEM, LBM_EDEVICE.  lbm_tape_end
+   s = 1 with post-collision storage; lbm_tape_begin on an LBM_FP32_HILO
+   lattice), LBM_ENOMEM, LBM_EDEVICE.  lbm_tape_end
    frees the checkpoints; lbm_set_state and lbm_set_initial drop the tape. */
 int lbm_tape_begin(lbm_handle* h, int64_t every);
 int lbm_tape_gradient(lbm_handle* h, const double* dl_dphi_dev, double* dl_dphi0_dev,

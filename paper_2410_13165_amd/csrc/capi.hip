@@ -137,6 +137,12 @@ void dev_free(lbm_handle* h, void* p) {
 
 size_t elem_size(int precision) { return precision == LBM_FP64 ? 8 : 4; }
 
+// the split layout: float32 g_k plus 8 bytes of phi per node (float64, or a
+// hi/lo pair of float32)
+bool split_mode(int precision) {
+  return precision == LBM_FP32_SPLIT || precision == LBM_FP32_HILO;
+}
+
 size_t pop_bytes(const lbm_handle* h) {
   return static_cast<size_t>(h->kp.pstride) * h->q * elem_size(h->precision);
 }
@@ -230,7 +236,7 @@ void setup_faces(KParams& kp, int d) {
 }
 
 size_t xdata_bytes(const lbm_handle* h) {
-  if (h->kp.bc[0] == LBM_BC_PERIODIC || h->precision != LBM_FP32_SPLIT) return 0;
+  if (h->kp.bc[0] == LBM_BC_PERIODIC || !split_mode(h->precision)) return 0;
   return sizeof(double) * 2 * (2 * h->d - 1) * static_cast<size_t>(h->kp.rows);
 }
 
@@ -259,21 +265,21 @@ int compute_reference(lbm_handle* h, const double* phi0) {
 }
 
 size_t state_bytes(const lbm_handle* h) {
-  return pop_bytes(h) + (h->precision == LBM_FP32_SPLIT ? phi_bytes(h) : 0);
+  return pop_bytes(h) + (split_mode(h->precision) ? phi_bytes(h) : 0);
 }
 
 // Device copy of the current state into a buffer of state_bytes(h).
 hipError_t copy_state_out(lbm_handle* h, void* dst) {
   hipError_t e = hipMemcpyAsync(dst, h->buf[h->cur], pop_bytes(h), hipMemcpyDeviceToDevice,
                                 h->stream);
-  if (e == hipSuccess && h->precision == LBM_FP32_SPLIT)
+  if (e == hipSuccess && split_mode(h->precision))
     e = hipMemcpyAsync(static_cast<char*>(dst) + pop_bytes(h), h->phib[h->cur], phi_bytes(h),
                        hipMemcpyDeviceToDevice, h->stream);
   return e;
 }
 
 double* blob_phi(const lbm_handle* h, void* blob) {
-  return (h->precision == LBM_FP32_SPLIT && blob)
+  return (split_mode(h->precision) && blob)
              ? reinterpret_cast<double*>(static_cast<char*>(blob) + pop_bytes(h))
              : nullptr;
 }
@@ -323,7 +329,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   if (d < 1 || d > kMaxDim) return fail(nullptr, LBM_EINVAL, "d must be in 1..4");
   if (!(tau > 0.0) || !std::isfinite(tau)) return fail(nullptr, LBM_EINVAL, "tau must be > 0");
   if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(nullptr, LBM_EINVAL, "dx must be > 0");
-  if (p->precision < LBM_FP64 || p->precision > LBM_FP32_SPLIT)
+  if (p->precision < LBM_FP64 || p->precision > LBM_FP32_HILO)
     return fail(nullptr, LBM_EINVAL, "unknown precision");
   if (p->init_order != 1 && p->init_order != 3)
     return fail(nullptr, LBM_EINVAL, "init_order must be 1 or 3");
@@ -378,7 +384,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   h->nodes = nodes;
   h->precision = p->precision;
   h->steps_per_pass =
-      (p->steps_per_pass == 2 && (d == 3 || (d == 2 && p->precision != LBM_FP32_SPLIT))) ? 2
+      (p->steps_per_pass == 2 && (d == 3 || (d == 2 && !split_mode(p->precision)))) ? 2
                                                                                         : 1;
   h->stream = static_cast<hipStream_t>(p->stream);
   if (hipGetDevice(&h->device) != hipSuccess) {
@@ -427,10 +433,13 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   kp.tau = tau;
   kp.s = 1.0 / tau;
   kp.s_f = static_cast<float>(kp.s);
+  kp.oms_f = static_cast<float>(1.0 - kp.s);
   kp.dx = p->dx;
   kp.dt = p->dx;  // c = 1
   kp.R = p->R;
   kp.dtR = kp.dt * kp.R;
+  kp.dtR_hi = static_cast<float>(kp.dtR);
+  kp.dtR_lo = static_cast<float>(kp.dtR - static_cast<double>(kp.dtR_hi));
   setup_faces(kp, d);
 
   // eps and omega: eq. (meq), eq. (meq-4rd) with g, closed form eq. (omega_k-2)
@@ -466,7 +475,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   const size_t pb = pop_bytes(h);
   for (int i = 0; i < 2; ++i) {
     h->buf[i] = dev_alloc(h, pb);
-    if (h->precision == LBM_FP32_SPLIT) h->phib[i] = static_cast<double*>(dev_alloc(h, phi_bytes(h)));
+    if (split_mode(h->precision)) h->phib[i] = static_cast<double*>(dev_alloc(h, phi_bytes(h)));
   }
   h->partial = static_cast<double*>(dev_alloc(h, sizeof(double) * kRedBlocks * kNumAcc));
   h->result = static_cast<double*>(dev_alloc(h, sizeof(double) * kNumAcc));
@@ -476,7 +485,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   bool ok = h->buf[0] && h->buf[1] && h->partial && h->result &&
             (h->check_every == 0 || h->nonfinite);
   if (xdata_bytes(h) > 0) ok = ok && kp.xdata;
-  if (h->precision == LBM_FP32_SPLIT) ok = ok && h->phib[0] && h->phib[1];
+  if (split_mode(h->precision)) ok = ok && h->phib[0] && h->phib[1];
   if (!ok) {
     release(h);
     delete h;
@@ -578,6 +587,8 @@ size_t pair_state_bytes(const lbm_handle* h) {
 hipError_t check_nonfinite(lbm_handle* h) {
   if (h->precision == LBM_FP32_SPLIT)
     return launch_count_nonfinite(h->phib[h->cur], true, h->nodes, h->nonfinite, h->stream);
+  if (h->precision == LBM_FP32_HILO)  // hi and lo of every node
+    return launch_count_nonfinite(h->phib[h->cur], false, 2 * h->nodes, h->nonfinite, h->stream);
   const bool dbl = h->precision == LBM_FP64;
   const size_t es = elem_size(h->precision);
   const int planes = h->kp.omega[0] == 0.0 ? 2 : 1;
@@ -709,7 +720,7 @@ int lbm_moments(lbm_handle* h, uint32_t what, double* phi_out_dev, double* scala
   const double nan = std::numeric_limits<double>::quiet_NaN();
   const bool sums = what & LBM_MOM_SUMS;
   const bool err = (what & LBM_MOM_RMSE) && h->kp.field.kind != kFieldNone;
-  const bool ent = (what & LBM_MOM_ENTROPY) && (h->precision == LBM_FP32_SPLIT || h->kp.s != 1.0);
+  const bool ent = (what & LBM_MOM_ENTROPY) && (split_mode(h->precision) || h->kp.s != 1.0);
   scalars_host[0] = sums ? acc[0] : nan;
   scalars_host[1] = sums ? acc[1] : nan;
   scalars_host[2] = err ? acc[2] : nan;
@@ -738,7 +749,7 @@ int lbm_info(const lbm_handle* h, lbm_info_t* out) {
   out->dt = h->kp.dt;
   out->phi_ref = h->kp.phi_ref;
   const int es = static_cast<int>(elem_size(h->precision));
-  out->bytes_per_lu = 2 * h->q * es + (h->precision == LBM_FP32_SPLIT ? 16 : 0);
+  out->bytes_per_lu = 2 * h->q * es + (split_mode(h->precision) ? 16 : 0);
   out->pstride = h->kp.pstride;
   out->steps_per_pass = h->steps_per_pass;
   return LBM_OK;
@@ -747,7 +758,7 @@ int lbm_info(const lbm_handle* h, lbm_info_t* out) {
 int64_t lbm_state_bytes(const lbm_handle* h) {
   if (!h) return -1;
   int64_t b = static_cast<int64_t>(pop_bytes(h));
-  if (h->precision == LBM_FP32_SPLIT) b += static_cast<int64_t>(phi_bytes(h));
+  if (split_mode(h->precision)) b += static_cast<int64_t>(phi_bytes(h));
   return b;
 }
 
@@ -756,7 +767,7 @@ int lbm_get_state(const lbm_handle* h, void* dst_dev) {
   lbm_handle* mh = const_cast<lbm_handle*>(h);
   hipError_t e = hipMemcpyAsync(dst_dev, h->buf[h->cur], pop_bytes(h), hipMemcpyDeviceToDevice,
                                 h->stream);
-  if (e == hipSuccess && h->precision == LBM_FP32_SPLIT)
+  if (e == hipSuccess && split_mode(h->precision))
     e = hipMemcpyAsync(static_cast<char*>(dst_dev) + pop_bytes(h), h->phib[h->cur], phi_bytes(h),
                        hipMemcpyDeviceToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(mh, e, "hipMemcpyAsync");
@@ -777,7 +788,7 @@ int set_state_impl(lbm_handle* h, const void* src_dev, int64_t step) {
   tape_clear(h);
   hipError_t e = hipMemcpyAsync(h->buf[h->cur], src_dev, pop_bytes(h), hipMemcpyDeviceToDevice,
                                 h->stream);
-  if (e == hipSuccess && h->precision == LBM_FP32_SPLIT)
+  if (e == hipSuccess && split_mode(h->precision))
     e = hipMemcpyAsync(h->phib[h->cur], static_cast<const char*>(src_dev) + pop_bytes(h),
                        phi_bytes(h), hipMemcpyDeviceToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync");
@@ -852,6 +863,8 @@ int lbm_tape_begin(lbm_handle* h, int64_t every) {
   if (!h->initialised) return fail(h, LBM_EINVAL, "no initial state");
   if (every < 1) return fail(h, LBM_EINVAL, "checkpoint interval must be >= 1");
   if (h->batch_member) return fail(h, LBM_EINVAL, "batch instances cannot record a tape");
+  if (h->precision == LBM_FP32_HILO)
+    return fail(h, LBM_EUNSUPPORTED, "tapes support LBM_FP64, LBM_FP32 and LBM_FP32_SPLIT");
   tape_clear(h);
   h->tape_start = h->step;
   h->tape_every = every;
@@ -1376,7 +1389,7 @@ int lbm_batch_create(int count, int d, const int64_t* dims, const double* tau,
   for (int i = 0; i < count; ++i) {
     if (params[i].precision != b->precision || params[i].stream != params[0].stream)
       return abort_create(bfail(nullptr, LBM_EINVAL, "batch instances need one precision and one stream"));
-    if (params[i].precision == LBM_FP32_SPLIT)
+    if (split_mode(params[i].precision))
       return abort_create(bfail(nullptr, LBM_EUNSUPPORTED, "batches support LBM_FP64 and LBM_FP32"));
     for (int a = 0; a < d; ++a)
       if (params[i].bc[a][0] != LBM_BC_PERIODIC || params[i].bc[a][1] != LBM_BC_PERIODIC)

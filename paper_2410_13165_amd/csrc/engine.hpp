@@ -17,7 +17,11 @@ constexpr int kRedThreads = 256;
 enum Scheme : int { kNoWall = 0, kFullWay = 1, kHalfWay = 2 };
 // work selected by the `what` mask of lbm_moments (the LBM_MOM_* bits)
 enum MomentBits : unsigned { kMomPhi = 1, kMomSums = 2, kMomRmse = 4, kMomEntropy = 8 };
-enum Mode : int { kFP64 = 0, kFP32 = 1, kSplit = 2 };
+// Storage modes (the values of lbm_precision).  kSplit and kHiLo share the
+// layout: float32 g_k = f_k - omega_k phi plus 8 bytes of phi per node
+// (float64, or an unevaluated float32 pair hi + lo).
+enum Mode : int { kFP64 = 0, kFP32 = 1, kSplit = 2, kHiLo = 3 };
+constexpr bool split_layout(int mode) { return mode == kSplit || mode == kHiLo; }
 enum FieldKind : int { kFieldNone = 0, kFieldCos = 1, kFieldExp = 2, kFieldTanh = 3 };
 
 // Analytic solution phi*(x, t) = F(x - u t) + R t (see include/lbm.h).
@@ -53,7 +57,9 @@ struct KParams {
   signed char cv[kMaxQ][kMaxDim];  // velocities (Sec. 2.3 order)
   int kbar[kMaxQ];                 // c_kbar = -c_k
   double s, tau, dt, dx, R;
-  double dtR;              // dt R, the source term of one step (split mode)
+  double dtR;              // dt R, the source term of one step (split modes)
+  float dtR_hi, dtR_lo;    // dt R as a float32 pair (hi/lo mode)
+  float oms_f;             // 1 - s in float32 (hi/lo mode)
   float s_f;
   double origin[kMaxDim];
   double shift[kMaxDim];   // 1/2 on half-way axes, else 0

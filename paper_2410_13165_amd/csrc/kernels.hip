@@ -89,9 +89,9 @@ void launch_xface(unsigned blocks, hipStream_t stream, T* buf, const KParams& p,
 template <int D, class T, bool TAN>
 void launch_wall(dim3 g, dim3 b, hipStream_t stream, const T* src, T* dst, const KParams& p,
                  double t);
-template <int D, bool TAN>
+template <int D, bool TAN, class PT>
 void launch_wall_split(dim3 g, dim3 b, hipStream_t stream, const float* gs, float* gd,
-                       const double* ps, double* pd, const KParams& p, double t);
+                       const PT* ps, PT* pd, const KParams& p, double t);
 
 template <int D, bool TAN>
 static hipError_t step_dt(const KParams& p, int mode, const void* src, void* dst,
@@ -128,13 +128,22 @@ static hipError_t step_dt(const KParams& p, int mode, const void* src, void* dst
     mark(1);
     if (p.wall_rows > 0)
       launch_wall<D, float, TAN>(wgrid, block, stream, a, b, p, t_n);
-  } else {
+  } else if (mode == kSplit) {
     auto* a = static_cast<const float*>(src);
     auto* b = static_cast<float*>(dst);
     hipLaunchKernelGGL((k_step_split<D>), grid, block, 0, stream, a, b, phi_src, phi_dst, p);
     mark(1);
     if (p.wall_rows > 0)
-      launch_wall_split<D, TAN>(wgrid, block, stream, a, b, phi_src, phi_dst, p, t_n);
+      launch_wall_split<D, TAN, double>(wgrid, block, stream, a, b, phi_src, phi_dst, p, t_n);
+  } else {
+    auto* a = static_cast<const float*>(src);
+    auto* b = static_cast<float*>(dst);
+    auto* pa = reinterpret_cast<const float2*>(phi_src);
+    auto* pb = reinterpret_cast<float2*>(phi_dst);
+    hipLaunchKernelGGL((k_step_hilo<D>), grid, block, 0, stream, a, b, pa, pb, p);
+    mark(1);
+    if (p.wall_rows > 0)
+      launch_wall_split<D, TAN, float2>(wgrid, block, stream, a, b, pa, pb, p, t_n);
   }
   mark(2);
   return hipGetLastError();
@@ -191,17 +200,18 @@ static hipError_t fused_pair_t(const KParams& p, const T* A, T* B, T* C, long lo
   return hipGetLastError();
 }
 
-template <bool TAN, bool HALF>
+template <bool TAN, bool HALF, bool HILO>
 static hipError_t fused_pair_split(const KParams& p, const FusedBufs& fb, long long n,
                                    hipStream_t stream, hipEvent_t* ev) {
   using S = FuseSplitShape<HALF>;
+  using PT = std::conditional_t<HILO, float2, double>;
   constexpr int R = (S::TX + 2) * (S::TY + 2);
   constexpr size_t lds = fuse_split_lds<HALF>();
   static_assert(lds <= 160 * 1024, "fused tile exceeds the LDS of a CU");
   static_assert((sizeof(float) * S::SLOTS * R) % 8 == 0, "phi planes must be 8-byte aligned");
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused2_split<HALF>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused2_split<HALF, HILO>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -210,6 +220,9 @@ static hipError_t fused_pair_split(const KParams& p, const FusedBufs& fb, long l
   auto* gA = static_cast<const float*>(fb.A);
   auto* gB = static_cast<float*>(fb.B);
   auto* gC = static_cast<float*>(fb.C);
+  auto* pA = reinterpret_cast<const PT*>(fb.phiA);
+  auto* pB = reinterpret_cast<PT*>(fb.phiB);
+  auto* pC = reinterpret_cast<PT*>(fb.phiC);
   const LaunchShape s = step_shape(p);
   const dim3 block(s.tx, s.ty);
   const dim3 wgrid(static_cast<unsigned>((p.wall_rows + s.ty - 1) / s.ty));
@@ -228,16 +241,16 @@ static hipError_t fused_pair_split(const KParams& p, const FusedBufs& fb, long l
     launch_xface<3, float, TAN>(xb, stream, gB, p2, t1, static_cast<int>(kSplit));
   }
   if (p.wall_rows > 0)
-    launch_wall_split<3, TAN>(wgrid, block, stream, gA, gC, fb.phiA, fb.phiC, p, t0);
+    launch_wall_split<3, TAN, PT>(wgrid, block, stream, gA, gC, pA, pC, p, t0);
   const int tiles_xy = ((p.n[0] + S::TX - 1) / S::TX) * ((p.n[1] + S::TY - 1) / S::TY);
   const int zc = fuse_zchunk(tiles_xy, p.n[2]);
   const dim3 grid(static_cast<unsigned>(tiles_xy * ((p.n[2] + zc - 1) / zc)));
   mark(0);
-  hipLaunchKernelGGL((k_fused2_split<HALF>), grid, dim3(S::NT), lds, stream, gA, gB, gC, fb.phiA,
-                     fb.phiB, fb.phiC, p, static_cast<const double*>(fb.xdata2), zc);
+  hipLaunchKernelGGL((k_fused2_split<HALF, HILO>), grid, dim3(S::NT), lds, stream, gA, gB, gC,
+                     pA, pB, pC, p, static_cast<const double*>(fb.xdata2), zc);
   mark(1);
   if (p.wall_rows > 0)
-    launch_wall_split<3, TAN>(wgrid, block, stream, gC, gB, fb.phiC, fb.phiB, p, t1);
+    launch_wall_split<3, TAN, PT>(wgrid, block, stream, gC, gB, pC, pB, p, t1);
   mark(2);
   return hipGetLastError();
 }
@@ -322,14 +335,21 @@ hipError_t launch_fused_pair(const KParams& p, int mode, const FusedBufs& fb, lo
   if (p.d != 3) return hipErrorInvalidValue;
   if (mode == kFP32) return fused_pair_m<float>(p, fb, n, stream, ev);
   if (mode == kFP64) return fused_pair_m<double>(p, fb, n, stream, ev);
-  if (mode == kSplit) {
+  if (split_layout(mode)) {
     if (p.bc[0] != 0 && !fb.xdata2) return hipErrorInvalidValue;
     const bool half = p.scheme == kHalfWay;
+    if (mode == kHiLo) {
+      if (p.wall_data)
+        return half ? fused_pair_split<true, true, true>(p, fb, n, stream, ev)
+                    : fused_pair_split<true, false, true>(p, fb, n, stream, ev);
+      return half ? fused_pair_split<false, true, true>(p, fb, n, stream, ev)
+                  : fused_pair_split<false, false, true>(p, fb, n, stream, ev);
+    }
     if (p.wall_data)
-      return half ? fused_pair_split<true, true>(p, fb, n, stream, ev)
-                  : fused_pair_split<true, false>(p, fb, n, stream, ev);
-    return half ? fused_pair_split<false, true>(p, fb, n, stream, ev)
-                : fused_pair_split<false, false>(p, fb, n, stream, ev);
+      return half ? fused_pair_split<true, true, false>(p, fb, n, stream, ev)
+                  : fused_pair_split<true, false, false>(p, fb, n, stream, ev);
+    return half ? fused_pair_split<false, true, false>(p, fb, n, stream, ev)
+                : fused_pair_split<false, false, false>(p, fb, n, stream, ev);
   }
   return hipErrorInvalidValue;
 }

@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(256)
       return;
     } else {
       if (cx != want) return;
-      if (mode == kSplit) {
+      if (split_layout(mode)) {
         p.xdata[((long long)side * S + xface_slot(D, k)) * p.rows + row] = val[k];
       } else {
         constexpr int kb = opp_index(D, k);
@@ -937,36 +937,112 @@ __device__ __forceinline__ double split_fstar_val(double omega, double phi, floa
   return split_fstar_t(omega, split_src(phi, p), g, p);
 }
 
-template <int D>
+// phi of a split-layout mode: float64, or (hi/lo mode) the unevaluated sum
+// hi + lo of two float32 with |lo| <= ulp(hi) / 2
+typedef float hilo_vec __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double phi_get(const double* __restrict__ ph, long long i) {
+  return ph[i];
+}
+__device__ __forceinline__ double phi_get(const float2* __restrict__ ph, long long i) {
+  const float2 v = ph[i];
+  return static_cast<double>(v.x) + static_cast<double>(v.y);
+}
+__device__ __forceinline__ float2 hilo_of(double v) {
+  const float h = static_cast<float>(v);
+  return make_float2(h, static_cast<float>(v - static_cast<double>(h)));
+}
+__device__ __forceinline__ void phi_put(double* __restrict__ ph, long long i, double v) {
+  __builtin_nontemporal_store(v, ph + i);
+}
+__device__ __forceinline__ void hilo_put(float2* __restrict__ ph, long long i, float2 v) {
+  const hilo_vec w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<hilo_vec*>(ph) + i);
+}
+__device__ __forceinline__ void phi_put(float2* __restrict__ ph, long long i, double v) {
+  hilo_put(ph, i, hilo_of(v));
+}
+
+template <int D, class PT>
 __device__ __forceinline__ void split_pull(double (&f)[q_of(D)], const float* __restrict__ gsrc,
-                                           const double* __restrict__ phisrc, long long ps,
+                                           const PT* __restrict__ phisrc, long long ps,
                                            int node, const RowInfo<D>& r, const KParams& p) {
   static_for<0, q_of(D)>([&](auto K) {
     constexpr int k = decltype(K)::value;
     const int idx = node + pull_offset<D, k>(r);
-    f[k] = split_fstar_val(p.omega[k], phisrc[idx], gsrc[k * ps + idx], p);
+    f[k] = split_fstar_val(p.omega[k], phi_get(phisrc, idx), gsrc[k * ps + idx], p);
   });
 }
 
-template <int D>
+template <int D, class PT>
 __device__ __forceinline__ double split_fstar(const float* __restrict__ gsrc,
-                                              const double* __restrict__ phisrc, long long ps,
+                                              const PT* __restrict__ phisrc, long long ps,
                                               int node, int kb, const KParams& p) {
-  return split_fstar_val(p.omega[kb], phisrc[node], gsrc[kb * ps + node], p);
+  return split_fstar_val(p.omega[kb], phi_get(phisrc, node), gsrc[kb * ps + node], p);
 }
 
-template <int D>
+template <int D, class PT>
 __device__ __forceinline__ void split_store(const double (&f)[q_of(D)], float* __restrict__ gdst,
-                                            double* __restrict__ phidst, long long ps, int node,
+                                            PT* __restrict__ phidst, long long ps, int node,
                                             const KParams& p) {
   constexpr int Q = q_of(D);
   double phi = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) phi += f[k];
-  __builtin_nontemporal_store(phi, phidst + node);
+  phi_put(phidst, node, phi);
 #pragma unroll
   for (int k = 0; k < Q; ++k)
     __builtin_nontemporal_store(static_cast<float>(f[k] - p.omega[k] * phi), gdst + k * ps + node);
+}
+
+// ---- hi/lo mode: the step in float32 arithmetic.  With b_k = f_k - omega_k
+// (phi(x) + dt R) at the node x being updated (sum_k omega_k = 1):
+//   bulk population, pulled from y = x - c_k:
+//     b_k = omega_k (phi(y) - phi(x)) + (1 - s) g_k(y),
+//     phi(y) - phi(x) = (hi(y) - hi(x)) + (lo(y) - lo(x)), nearly exact for
+//     neighbouring values (Sterbenz);
+//   population set by a wall scheme to the value v (float64):
+//     b_k = v - omega_k (phi(x) + dt R);
+//   beta = sum_k b_k, phi_new = phi(x) + dt R + beta, g_new_k = b_k - omega_k beta.
+// dt R enters phi only, as an exact float32 pair added with error-free sums
+// (rounded to float32 it would add the same error every step and drift
+// linearly); the float32 rounding left is that of beta, the transport part
+// of the update.  Every kernel of the mode uses these helpers (two-step
+// passes equal single steps bit for bit); rows on walls of x_2.. go through
+// the float64 split formulas (split_pull / split_store on the pair), in
+// single steps and pairs alike.
+__device__ __forceinline__ float hilo_b(float omega, float2 py, float2 own, float g,
+                                       const KParams& p) {
+  const float dk = (py.x - own.x) + (py.y - own.y);
+  return fmaf(omega, dk, p.oms_f * g);
+}
+
+__device__ __forceinline__ void two_sum_f(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+// (hi + lo) + (dtR_hi + dtR_lo) + beta as a normalised pair
+__device__ __forceinline__ float2 hilo_advance(float2 v, float beta, const KParams& p) {
+  float s1, e1, s2, e2;
+  two_sum_f(v.x, p.dtR_hi, s1, e1);
+  two_sum_f(s1, beta, s2, e2);
+  const float lo = ((v.y + p.dtR_lo) + e1) + e2;
+  const float h = s2 + lo;
+  return make_float2(h, lo - (h - s2));
+}
+
+template <int D>
+__device__ __forceinline__ void hilo_finish(const float (&b)[q_of(D)], float2 own, float2& phi_new,
+                                            float (&g)[q_of(D)], const KParams& p) {
+  constexpr int Q = q_of(D);
+  float beta = 0.0f;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) beta += b[k];
+  phi_new = hilo_advance(own, beta, p);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) g[k] = fmaf(-p.omega_f[k], beta, b[k]);
 }
 
 template <int D>
@@ -1005,6 +1081,57 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// One step of the hi/lo mode (the b_k form above).
+template <int D>
+__global__ void __launch_bounds__(256)
+    k_step_hilo(const float* __restrict__ gsrc, float* __restrict__ gdst,
+                const float2* __restrict__ phisrc, float2* __restrict__ phidst, const KParams p) {
+  constexpr int Q = q_of(D);
+  constexpr int S = 2 * D - 1;
+  const int row = blockIdx.x * blockDim.y + threadIdx.y;
+  if (row >= p.rows) return;
+  RowInfo<D> r;
+  row_setup<D>(p, row, r);
+  if (r.rowwall) return;
+  const long long ps = p.pstride;
+  const bool half = p.scheme == kHalfWay;
+  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+    col_setup<D>(p, x, r);
+    const int node = r.rowbase + x;
+    const float2 own = phisrc[node];
+    float b[Q];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      const int idx = node + pull_offset<D, k>(r);
+      b[k] = hilo_b(p.omega_f[k], phisrc[idx], own, gsrc[k * ps + idx], p);
+    });
+    if (r.lo[0] || r.hi[0]) {
+      const double phx = static_cast<double>(own.x) + static_cast<double>(own.y);
+      const double* W = p.xdata + (r.hi[0] ? S * p.rows : 0) + row;
+      static_for<0, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr int cx = vel_comp(D, k, 0);
+        if constexpr (cx != 0) {
+          if ((cx == 1) ? r.lo[0] : r.hi[0]) {
+            double v = W[(long long)xface_slot(D, k) * p.rows];
+            if (half) {
+              constexpr int kb = opp_index(D, k);
+              v -= split_fstar_val(p.omega[kb], phx, gsrc[kb * ps + node], p);
+            }
+            b[k] = static_cast<float>(v - p.omega[k] * (phx + p.dtR));
+          }
+        }
+      });
+    }
+    float2 phi_new;
+    float g[Q];
+    hilo_finish<D>(b, own, phi_new, g, p);
+    hilo_put(phidst, node, phi_new);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(g[k], gdst + k * ps + node);
+  }
+}
+
 // Two fused steps of the split representation (d = 3), organised as k_fused2:
 // the LDS keeps the step-1 g_k (float32, the same plane slots) and
 // t = split_src(phi) (float64, a ring of three planes).  The x_1-face data of
@@ -1037,21 +1164,25 @@ constexpr size_t fuse_split_lds() {
          sizeof(double) * 3 * (S::TX + 4) * (S::TY + 4);
 }
 
-template <bool HALF>
+// HILO: the hi/lo mode, whose rings hold the (hi, lo) pairs of phi instead of t.
+template <bool HALF, bool HILO>
 __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
     k_fused2_split(const float* __restrict__ gA, float* __restrict__ gB, float* __restrict__ gC,
-                   const double* __restrict__ phiA, double* __restrict__ phiB,
-                   double* __restrict__ phiC, const KParams p, const double* __restrict__ xd2,
-                   const int zc) {
+                   const std::conditional_t<HILO, float2, double>* __restrict__ phiA,
+                   std::conditional_t<HILO, float2, double>* __restrict__ phiB,
+                   std::conditional_t<HILO, float2, double>* __restrict__ phiC, const KParams p,
+                   const double* __restrict__ xd2, const int zc) {
   using S = FuseSplitShape<HALF>;
+  using PT = std::conditional_t<HILO, float2, double>;
+  static_assert(sizeof(PT) == sizeof(double), "both rings hold 8 bytes per node");
   constexpr int D = 3, Q = q_of(3), TX = S::TX, TY = S::TY, NT = S::NT;
   constexpr int RX = TX + 2, RY = TY + 2, R = RX * RY;
   constexpr int PX = TX + 4, PY = TY + 4, P2 = PX * PY;
   constexpr int SX = 2 * D - 1;
   extern __shared__ __align__(16) unsigned char fuse_lds[];
   float* lg = reinterpret_cast<float*>(fuse_lds);
-  double* lphi = reinterpret_cast<double*>(fuse_lds + sizeof(float) * S::SLOTS * R);
-  double* lsrc = lphi + 3 * R;
+  PT* lphi = reinterpret_cast<PT*>(fuse_lds + sizeof(float) * S::SLOTS * R);
+  PT* lsrc = lphi + 3 * R;
   const long long ps = p.pstride;
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
   int tx_, ty_, tz_;
@@ -1059,7 +1190,12 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
   const int x0 = tx_ * TX, y0 = ty_ * TY, zc0 = tz_ * zc;
   const int zend = min(zc0 + zc, n2);
   const int iters = zend - zc0 + 2;
-  // t of the source phi of plane z (zc0 - 2 <= z <= zend + 1) into ring slot
+  // ring value of a node's phi: t = split_src(phi), or the hi/lo pair itself
+  auto ring_val = [&](PT v) -> PT {
+    if constexpr (HILO) return v;
+    else return split_src(v, p);
+  };
+  // the source phi of plane z (zc0 - 2 <= z <= zend + 1) into ring slot
   // (z - zc0 + 2) mod 3, at (x_1, x_2) = (x0 - 2 + sx, y0 - 2 + sy).  Positions
   // outside a Dirichlet axis stay unwritten: they are read only by pulls that
   // the x_1-face data replace (rows on the walls of x_2 / x_3 pull nothing).
@@ -1069,7 +1205,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
       if (p.bc[2] != 0) return;
       gz = fuse_wrap(gz, n2);
     }
-    double* dst = lsrc + ((z - zc0 + 2) % 3) * P2;
+    PT* dst = lsrc + ((z - zc0 + 2) % 3) * P2;
     for (int t = threadIdx.x; t < P2; t += NT) {
       const int sx = t % PX, sy = t / PX;
       int gx = x0 - 2 + sx, gy = y0 - 2 + sy;
@@ -1081,7 +1217,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
         if (p.bc[1] != 0) continue;
         gy = fuse_wrap(gy, n1);
       }
-      dst[t] = split_src(phiA[(static_cast<long long>(gz) * n1 + gy) * n0 + gx], p);
+      dst[t] = ring_val(phiA[(static_cast<long long>(gz) * n1 + gy) * n0 + gx]);
     }
   };
   stage(zc0 - 2);
@@ -1114,7 +1250,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
       col_setup<D>(p, gx, ri);
       const int node = ri.rowbase + gx;
       float g[Q];
-      double phi;
+      PT phi;
       if (ri.rowwall) {
         phi = phiC[node];
         static_for<0, Q>([&](auto K) {
@@ -1122,47 +1258,79 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
           g[k] = gC[k * ps + node];
         });
       } else {
-        // split_pull with phi from the source ring: plane zp - c_3 is in
-        // slot (it + 1 - c_3) mod 3
+        // the pull with phi from the source ring: plane zp - c_3 is in slot
+        // (it + 1 - c_3) mod 3
         const int sown = (ry + 1) * PX + rx + 1;
-        const double* s0 = lsrc + ((it + 1) % 3) * P2 + sown;
-        double f[Q];
-        static_for<0, Q>([&](auto K) {
-          constexpr int k = decltype(K)::value;
-          constexpr Vec4i c = vel_vec(D, k);
-          const double* sp = c.v[2] == 0 ? s0 : lsrc + ((it + 1 - c.v[2]) % 3) * P2 + sown;
-          const double ph = sp[-c.v[1] * PX - c.v[0]];
-          f[k] = split_fstar_t(p.omega[k], ph, gA[k * ps + node + pull_offset<D, k>(ri)], p);
-        });
-        if (ri.lo[0] || ri.hi[0]) {
-          const double* W = p.xdata + (ri.hi[0] ? SX * p.rows : 0) + row;
+        const PT* s0 = lsrc + ((it + 1) % 3) * P2 + sown;
+        if constexpr (HILO) {
+          const float2 own = *s0;
+          const double phx = static_cast<double>(own.x) + static_cast<double>(own.y);
+          float b[Q];
           static_for<0, Q>([&](auto K) {
             constexpr int k = decltype(K)::value;
-            constexpr int cx = vel_comp(D, k, 0);
-            if constexpr (cx != 0) {
-              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
-                double v = W[(long long)xface_slot(D, k) * p.rows];
-                if (HALF) {
-                  constexpr int kb = opp_index(D, k);
-                  v -= split_fstar_t(p.omega[kb], *s0, gA[kb * ps + node], p);
-                }
-                f[k] = v;
-              }
-            }
+            constexpr Vec4i c = vel_vec(D, k);
+            const PT* sp = c.v[2] == 0 ? s0 : lsrc + ((it + 1 - c.v[2]) % 3) * P2 + sown;
+            b[k] = hilo_b(p.omega_f[k], sp[-c.v[1] * PX - c.v[0]], own,
+                          gA[k * ps + node + pull_offset<D, k>(ri)], p);
           });
+          if (ri.lo[0] || ri.hi[0]) {
+            const double* W = p.xdata + (ri.hi[0] ? SX * p.rows : 0) + row;
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                  double v = W[(long long)xface_slot(D, k) * p.rows];
+                  if (HALF) {
+                    constexpr int kb = opp_index(D, k);
+                    v -= split_fstar_val(p.omega[kb], phx, gA[kb * ps + node], p);
+                  }
+                  b[k] = static_cast<float>(v - p.omega[k] * (phx + p.dtR));
+                }
+              }
+            });
+          }
+          hilo_finish<D>(b, own, phi, g, p);
+        } else {
+          double f[Q];
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr Vec4i c = vel_vec(D, k);
+            const PT* sp = c.v[2] == 0 ? s0 : lsrc + ((it + 1 - c.v[2]) % 3) * P2 + sown;
+            const double ph = sp[-c.v[1] * PX - c.v[0]];
+            f[k] = split_fstar_t(p.omega[k], ph, gA[k * ps + node + pull_offset<D, k>(ri)], p);
+          });
+          if (ri.lo[0] || ri.hi[0]) {
+            const double* W = p.xdata + (ri.hi[0] ? SX * p.rows : 0) + row;
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                  double v = W[(long long)xface_slot(D, k) * p.rows];
+                  if (HALF) {
+                    constexpr int kb = opp_index(D, k);
+                    v -= split_fstar_t(p.omega[kb], *s0, gA[kb * ps + node], p);
+                  }
+                  f[k] = v;
+                }
+              }
+            });
+          }
+          // split_store's arithmetic, into registers
+          phi = 0.0;
+#pragma unroll
+          for (int k = 0; k < Q; ++k) phi += f[k];
+#pragma unroll
+          for (int k = 0; k < Q; ++k) g[k] = static_cast<float>(f[k] - p.omega[k] * phi);
         }
-        // split_store's arithmetic, into registers
-        phi = 0.0;
-#pragma unroll
-        for (int k = 0; k < Q; ++k) phi += f[k];
-#pragma unroll
-        for (int k = 0; k < Q; ++k) g[k] = static_cast<float>(f[k] - p.omega[k] * phi);
         const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
                          y0 - 1 + ry < n1 && zp >= zc0 && zp < zend;
         const bool near = (p.bc[1] != 0 && (ri.i[1] == 1 || ri.i[1] == n1 - 2)) ||
                           (p.bc[2] != 0 && (ri.i[2] == 1 || ri.i[2] == n2 - 2));
         if (own && near) {
-          __builtin_nontemporal_store(phi, phiC + node);
+          if constexpr (HILO) hilo_put(phiC, node, phi);
+          else __builtin_nontemporal_store(phi, phiC + node);
 #pragma unroll
           for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(g[k], gC + k * ps + node);
         }
@@ -1171,7 +1339,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
         constexpr int k = decltype(K)::value;
         lg[fuse_slot<HALF, k>(it) * R + r] = g[k];
       });
-      lphi[(it % 3) * R + r] = split_src(phi, p);
+      lphi[(it % 3) * R + r] = ring_val(phi);
     }
     __syncthreads();
     if (it >= 2) {
@@ -1186,37 +1354,75 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
         if (ri.rowwall) continue;
         col_setup<D>(p, gx, ri);
         const int node = ri.rowbase + gx;
-        double f[Q];
-        static_for<0, Q>([&](auto K) {
-          constexpr int k = decltype(K)::value;
-          constexpr Vec4i c = vel_vec(D, k);
-          constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
-          const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
-          const double ph = lphi[((it - src_it) % 3) * R + rr];
-          const float gk = lg[fuse_slot<HALF, k>(it - src_it) * R + rr];
-          f[k] = split_fstar_t(p.omega[k], ph, gk, p);
-        });
-        if (ri.lo[0] || ri.hi[0]) {
-          const double* W = xd2 + (ri.hi[0] ? SX * p.rows : 0) + row;
-          const int own = (oy + 1) * RX + (ox + 1);
+        const int own = (oy + 1) * RX + (ox + 1);
+        if constexpr (HILO) {
+          const float2 me = lphi[((it - 1) % 3) * R + own];
+          const double phx = static_cast<double>(me.x) + static_cast<double>(me.y);
+          float b[Q];
           static_for<0, Q>([&](auto K) {
             constexpr int k = decltype(K)::value;
-            constexpr int cx = vel_comp(D, k, 0);
-            if constexpr (cx != 0) {
-              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
-                double v = W[(long long)xface_slot(D, k) * p.rows];
-                if constexpr (HALF) {
-                  constexpr int kb = opp_index(D, k);
-                  const double ph = lphi[((it - 1) % 3) * R + own];
-                  const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
-                  v -= split_fstar_t(p.omega[kb], ph, gb, p);
-                }
-                f[k] = v;
-              }
-            }
+            constexpr Vec4i c = vel_vec(D, k);
+            constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
+            const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
+            b[k] = hilo_b(p.omega_f[k], lphi[((it - src_it) % 3) * R + rr], me,
+                          lg[fuse_slot<HALF, k>(it - src_it) * R + rr], p);
           });
+          if (ri.lo[0] || ri.hi[0]) {
+            const double* W = xd2 + (ri.hi[0] ? SX * p.rows : 0) + row;
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                  double v = W[(long long)xface_slot(D, k) * p.rows];
+                  if constexpr (HALF) {
+                    constexpr int kb = opp_index(D, k);
+                    const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
+                    v -= split_fstar_val(p.omega[kb], phx, gb, p);
+                  }
+                  b[k] = static_cast<float>(v - p.omega[k] * (phx + p.dtR));
+                }
+              }
+            });
+          }
+          float2 phi_new;
+          float g[Q];
+          hilo_finish<D>(b, me, phi_new, g, p);
+          hilo_put(phiB, node, phi_new);
+#pragma unroll
+          for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(g[k], gB + k * ps + node);
+        } else {
+          double f[Q];
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr Vec4i c = vel_vec(D, k);
+            constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
+            const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
+            const double ph = lphi[((it - src_it) % 3) * R + rr];
+            const float gk = lg[fuse_slot<HALF, k>(it - src_it) * R + rr];
+            f[k] = split_fstar_t(p.omega[k], ph, gk, p);
+          });
+          if (ri.lo[0] || ri.hi[0]) {
+            const double* W = xd2 + (ri.hi[0] ? SX * p.rows : 0) + row;
+            static_for<0, Q>([&](auto K) {
+              constexpr int k = decltype(K)::value;
+              constexpr int cx = vel_comp(D, k, 0);
+              if constexpr (cx != 0) {
+                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                  double v = W[(long long)xface_slot(D, k) * p.rows];
+                  if constexpr (HALF) {
+                    constexpr int kb = opp_index(D, k);
+                    const double ph = lphi[((it - 1) % 3) * R + own];
+                    const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
+                    v -= split_fstar_t(p.omega[kb], ph, gb, p);
+                  }
+                  f[k] = v;
+                }
+              }
+            });
+          }
+          split_store<D>(f, gB, phiB, ps, node, p);
         }
-        split_store<D>(f, gB, phiB, ps, node, p);
       }
     }
     // the next iteration's source plane zp + 2 replaces plane zp - 1, which
@@ -1284,10 +1490,10 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <int D, bool TAN, int V>
+template <int D, bool TAN, int V, class PT>
 __global__ void __launch_bounds__(256)
     k_wall_split(const float* __restrict__ gsrc, float* __restrict__ gdst,
-                 const double* __restrict__ phisrc, double* __restrict__ phidst, const KParams p,
+                 const PT* __restrict__ phisrc, PT* __restrict__ phidst, const KParams p,
                  const double t_n) {
   constexpr int Q = q_of(D);
   const int widx = blockIdx.x * blockDim.y + threadIdx.y;
@@ -1377,8 +1583,11 @@ __global__ void __launch_bounds__(256)
     double sum = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) sum += f[k];
-    if (mode == kSplit) {
-      phidst[node] = sum;
+    if (split_layout(mode)) {
+      if (mode == kHiLo)
+        reinterpret_cast<float2*>(phidst)[node] = hilo_of(sum);
+      else
+        phidst[node] = sum;
 #pragma unroll
       for (int k = 0; k < Q; ++k)
         reinterpret_cast<float*>(dst)[k * ps + node] = static_cast<float>(f[k] - p.omega[k] * sum);
@@ -1439,8 +1648,8 @@ __global__ void __launch_bounds__(kRedThreads)
        node += gridDim.x * blockDim.x) {
     double fk[Q];
     double phi;
-    if (mode == kSplit) {
-      phi = phis[node];
+    if (split_layout(mode)) {
+      phi = mode == kHiLo ? phi_get(reinterpret_cast<const float2*>(phis), node) : phis[node];
       const float* g = reinterpret_cast<const float*>(f);
 #pragma unroll
       for (int k = 0; k < Q; ++k) fk[k] = static_cast<double>(g[k * ps + node]) + p.omega[k] * phi;

@@ -1,5 +1,6 @@
 // Launches of the wall-row (k_wall, k_wall_split) and x_1-face (k_xface)
-// kernels, compiled per wall-formula variant for d = 2 and 3.  The explicit
+// kernels, compiled per wall-formula variant for d = 2 and 3 (k_wall_split
+// for both split-layout modes).  The explicit
 // instantiations are spread over walls_d*.hip, translation units of their own
 // that compile in parallel with each other and with the bulk kernels.
 #pragma once
@@ -41,24 +42,25 @@ void launch_wall(dim3 g, dim3 b, hipStream_t stream, const T* src, T* dst, const
   }
 }
 
-template <int D, bool TAN>
+// PT: the phi of the split layout, double (split mode) or float2 (hi/lo mode)
+template <int D, bool TAN, class PT>
 void launch_wall_split(dim3 g, dim3 b, hipStream_t stream, const float* gs, float* gd,
-                       const double* ps, double* pd, const KParams& p, double t) {
+                       const PT* ps, PT* pd, const KParams& p, double t) {
   if constexpr (D == 1 || D == 4) {
-    hipLaunchKernelGGL((k_wall_split<D, TAN, -1>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+    hipLaunchKernelGGL((k_wall_split<D, TAN, -1, PT>), g, b, 0, stream, gs, gd, ps, pd, p, t);
   } else {
     switch (wall_variant(p)) {
       case 0:
-        hipLaunchKernelGGL((k_wall_split<D, TAN, 0>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+        hipLaunchKernelGGL((k_wall_split<D, TAN, 0, PT>), g, b, 0, stream, gs, gd, ps, pd, p, t);
         break;
       case 1:
-        hipLaunchKernelGGL((k_wall_split<D, TAN, 1>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+        hipLaunchKernelGGL((k_wall_split<D, TAN, 1, PT>), g, b, 0, stream, gs, gd, ps, pd, p, t);
         break;
       case 2:
-        hipLaunchKernelGGL((k_wall_split<D, TAN, 2>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+        hipLaunchKernelGGL((k_wall_split<D, TAN, 2, PT>), g, b, 0, stream, gs, gd, ps, pd, p, t);
         break;
       default:
-        hipLaunchKernelGGL((k_wall_split<D, TAN, 3>), g, b, 0, stream, gs, gd, ps, pd, p, t);
+        hipLaunchKernelGGL((k_wall_split<D, TAN, 3, PT>), g, b, 0, stream, gs, gd, ps, pd, p, t);
     }
   }
 }
@@ -72,7 +74,11 @@ void launch_wall_split(dim3 g, dim3 b, hipStream_t stream, const float* gs, floa
                                            const KParams&, double);                    \
   template void launch_wall<D, double, TAN>(dim3, dim3, hipStream_t, const double*,       \
                                             double*, const KParams&, double);          \
-  template void launch_wall_split<D, TAN>(dim3, dim3, hipStream_t, const float*, float*,   \
-                                          const double*, double*, const KParams&, double);
+  template void launch_wall_split<D, TAN, double>(dim3, dim3, hipStream_t, const float*,  \
+                                                  float*, const double*, double*,          \
+                                                  const KParams&, double);                 \
+  template void launch_wall_split<D, TAN, float2>(dim3, dim3, hipStream_t, const float*,  \
+                                                  float*, const float2*, float2*,          \
+                                                  const KParams&, double);
 
 }  // namespace lbm

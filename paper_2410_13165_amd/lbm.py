@@ -25,7 +25,7 @@ NSCALARS = 8
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5
 MOM_PHI, MOM_SUMS, MOM_RMSE, MOM_ENTROPY, MOM_ALL = 1, 2, 4, 8, 15
 BC = {"periodic": 0, "fullway": 1, "halfway": 2}
-PRECISION = {"fp64": 0, "fp32": 1, "fp32_split": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_split": 2, "fp32_hilo": 3}
 WALL_DATA = {"jets": 0, "tangential": 1}
 FIELD = {"none": 0, "cos_sum": 1, "exp_sum": 2, "tanh_bubble": 3}
 BATCH_LAUNCH = {"per_pair": 0, "resident": 1}

@@ -56,7 +56,7 @@ def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
 def gpu_populations(lat, info=None) -> np.ndarray:
     """Stored state of a GPU lattice as absolute populations in oracle order.
 
-    fp64 / fp32: post-collision f*(t_n); fp32_split: pre-collision f(t_n).
+    fp64 / fp32: post-collision f*(t_n); fp32_split, fp32_hilo: pre-collision f(t_n).
     Returns shape (q, N_1, ..., N_d)."""
     import torch
     info = info or lat.info()
@@ -77,6 +77,10 @@ def gpu_populations(lat, info=None) -> np.ndarray:
         f = f + omega[:, None] * ref
     if lat.precision == "fp32_split":
         phi = blob[q * pstride * 4:].view(torch.float64).cpu().numpy()[:nodes]
+        f = f + omega[:, None] * phi[None, :]
+    if lat.precision == "fp32_hilo":
+        hl = blob[q * pstride * 4:].view(torch.float32).cpu().numpy()[:2 * nodes]
+        phi = hl[0::2].astype(np.float64) + hl[1::2].astype(np.float64)
         f = f + omega[:, None] * phi[None, :]
     out = np.empty((q,) + tuple(lat.dims))
     for k in range(q):

@@ -294,6 +294,18 @@ def test_gradient_workload_full_size_identity(prec):
     assert rel <= 1e-6
 
 
+def test_tape_refused_in_hilo_mode():
+    """The hi/lo mode has no adjoint: lbm_tape_begin says so."""
+    from paper_2410_13165_amd import LbmError
+    spec = inputs.random_cosines(3, [0.05, -0.1, 0.08], 0.4, seed=77, kmax=1.0)
+    lat = gpu_lattice(3, (12, 10, 9), 1.0 / 12, spec, precision="fp32_hilo")
+    try:
+        with pytest.raises(LbmError, match="tapes support"):
+            lat.tape_begin(4)
+    finally:
+        lat.close()
+
+
 def test_tape_cleared_by_set_state_and_set_initial():
     """A tape describes the run recorded since lbm_tape_begin: replacing the
     state (lbm_set_state) or the initial field (lbm_set_initial) drops it, so

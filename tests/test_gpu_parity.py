@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-TOL = {"fp64": 1e-12, "fp32": 2e-5, "fp32_split": 2e-5}
+TOL = {"fp64": 1e-12, "fp32": 2e-5, "fp32_split": 2e-5, "fp32_hilo": 2e-5}
 
 
 def _phi(lat):
@@ -63,7 +63,7 @@ def test_periodic_fp64(d, dims, tau):
 
 
 @pytest.mark.parametrize("d,dims", [(2, (130, 67)), (3, (70, 33, 17))])
-@pytest.mark.parametrize("precision", ["fp32", "fp32_split"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_split", "fp32_hilo"])
 def test_periodic_reduced_precision(d, dims, precision):
     spec = inputs.random_cosines(d, [0.1, 0.2, 0.08][:d], 0.4, seed=10 + d)
     _check_pair(d, dims, 1.0 / dims[0], spec, 60, precision=precision)
@@ -99,7 +99,7 @@ def test_mixed_periodic_and_dirichlet_axes(scheme):
 
 
 @pytest.mark.parametrize("scheme", ["fullway", "halfway"])
-@pytest.mark.parametrize("precision", ["fp32", "fp32_split"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_split", "fp32_hilo"])
 def test_dirichlet_reduced_precision(scheme, precision):
     spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0, seed=41, kmax=1.0)
     _check_pair(3, (45, 22, 19), 1.0 / 44, spec, 80, bc=[scheme] * 3, precision=precision)
@@ -126,7 +126,7 @@ def test_tangential_wall_data(scheme, d, dims):
         b.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp32_split"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_split", "fp32_hilo"])
 def test_tangential_wall_data_reduced_precision_and_lower_order(precision):
     spec = inputs.example1([0.1, 0.1])
     _check_pair(2, (21, 21), 1.0 / 20, spec, 40, bc=["fullway"] * 2, P=3,
@@ -139,7 +139,7 @@ def test_tangential_wall_data_reduced_precision_and_lower_order(precision):
 
 
 def _node_state(lat):
-    """Populations (split mode: g_k and phi) of the nodes, without the padding
+    """Populations (split modes: g_k and the 8 bytes of phi) of the nodes, without the padding
     and x_1-face slots of the state blob."""
     info = lat.info()
     q, ps, nodes = info["q"], info["pstride"], info["nodes"]
@@ -165,7 +165,7 @@ def _node_state(lat):
     ((3, 2, 5), ["fullway"] * 3, "jets"),
     ((5, 4, 3), ["periodic"] * 3, "jets"),
 ])
-@pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32_split"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32_split", "fp32_hilo"])
 def test_two_step_passes_equal_single_steps_bitwise(dims, bc, wall_data, precision):
     """d = 3: steps taken two per bulk pass (intermediate state in LDS) give
     bitwise the populations of single steps, for periodic, full-way, half-way
@@ -240,6 +240,7 @@ def test_example1_source_term_fp32_reference():
     spec = inputs.example1([0.1, 0.1])
     _check_pair(2, (41, 41), 1.0 / 40, spec, 200, bc=["fullway"] * 2, precision="fp32")
     _check_pair(2, (41, 41), 1.0 / 40, spec, 200, bc=["fullway"] * 2, precision="fp32_split")
+    _check_pair(2, (41, 41), 1.0 / 40, spec, 200, bc=["fullway"] * 2, precision="fp32_hilo")
 
 
 @pytest.mark.parametrize("scheme", ["fullway", "halfway"])
@@ -298,7 +299,7 @@ def test_set_initial_with_gradient():
 
 # ----------------------------------------------------------- diagnostics ---
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_split"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_split", "fp32_hilo"])
 def test_diagnostics_match_oracle(precision):
     spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0, seed=51, kmax=1.0)
     dims = (33, 17, 12)
@@ -337,7 +338,7 @@ def test_entropy_conserved_on_gpu_and_nan_at_tau_one():
 
 # -------------------------------------------------------- state and edges ---
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_split"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_split", "fp32_hilo"])
 def test_checkpoint_roundtrip_is_bitwise(precision):
     spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0, seed=71, kmax=1.0)
     kw = dict(bc=["fullway"] * 3, precision=precision)
@@ -403,8 +404,8 @@ def test_zero_steps_and_error_reporting():
 # ------------------------------------------------------- full-size check ---
 
 @pytest.mark.parametrize("precision,scheme", [("fp32", "fullway"), ("fp64", "fullway"),
-                                              ("fp32_split", "fullway"), ("fp32", "halfway"),
-                                              ("fp64", "halfway")])
+                                              ("fp32_split", "fullway"), ("fp32_hilo", "fullway"),
+                                              ("fp32", "halfway"), ("fp64", "halfway")])
 def test_benchmark_configuration_sampled(precision, scheme):
     """D3Q19, 512^3 nodes, full-way (the benchmark) or half-way walls on all
     faces, in the benchmark's launch configuration (a two-step pass, then one
@@ -559,7 +560,7 @@ def _checked_lattice(precision, n, check_every, bc="halfway"):
 
 
 @pytest.mark.parametrize("precision,steps", [("fp32", 1000), ("fp64", 6000),
-                                             ("fp32_split", 6000)])
+                                             ("fp32_split", 6000), ("fp32_hilo", 6000)])
 def test_nonfinite_check_reports_blow_up(precision, steps):
     """Table 1's diverging row (half-way walls at u = (0.4, 0.4), Example 1,
     80 nodes per axis): the values overflow (float32 within 1000 steps, float64
@@ -582,7 +583,7 @@ def test_nonfinite_check_catches_nan_initial_field():
     from paper_2410_13165_amd import lbm as B
     phi0 = torch.from_numpy(inputs.noise((40, 48), seed=3))
     phi0[17, 5] = float("nan")
-    for precision in ("fp64", "fp32", "fp32_split"):
+    for precision in ("fp64", "fp32", "fp32_split", "fp32_hilo"):
         lat = Lattice(2, (48, 40), 0.5, dx=1 / 48, u=[0.1, 0.2], precision=precision,
                       check_every=4)
         try:
@@ -595,7 +596,7 @@ def test_nonfinite_check_catches_nan_initial_field():
             lat.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_split"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_split", "fp32_hilo"])
 def test_nonfinite_check_leaves_results_unchanged(precision):
     a = _checked_lattice(precision, 40, 3, bc="fullway")
     b = _checked_lattice(precision, 40, 0, bc="fullway")
