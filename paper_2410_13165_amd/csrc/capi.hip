@@ -457,6 +457,7 @@ int lbm_create(int d, const int64_t* dims, double tau, const lbm_params* p, lbm_
   h->min_omega = kp.omega[0];
   for (int k = 0; k < h->q; ++k) {
     kp.omega_f[k] = static_cast<float>(kp.omega[k]);
+    kp.omega_lo[k] = static_cast<float>(kp.omega[k] - static_cast<double>(kp.omega_f[k]));
     h->min_omega = std::fmin(h->min_omega, kp.omega[k]);
   }
   h->entropy_stable = h->min_omega > 0.0 ? 1 : 0;

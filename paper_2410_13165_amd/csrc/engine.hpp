@@ -54,6 +54,7 @@ struct KParams {
   int K;                   // initialisation order
   double omega[kMaxQ];
   float omega_f[kMaxQ];
+  float omega_lo[kMaxQ];    // omega - omega_f, rounded (hi/lo mode)
   signed char cv[kMaxQ][kMaxDim];  // velocities (Sec. 2.3 order)
   int kbar[kMaxQ];                 // c_kbar = -c_k
   double s, tau, dt, dx, R;

@@ -1011,10 +1011,11 @@ __device__ __forceinline__ void split_store(const double (&f)[q_of(D)], float* _
 // passes equal single steps bit for bit); rows on walls of x_2.. go through
 // the float64 split formulas (split_pull / split_store on the pair), in
 // single steps and pairs alike.
-__device__ __forceinline__ float hilo_b(float omega, float2 py, float2 own, float g,
-                                       const KParams& p) {
+// omega_k enters as the float32 pair omega_f + omega_lo: rounded to float32
+// alone it would perturb the stencil weights the same way every step
+__device__ __forceinline__ float hilo_b(int k, float2 py, float2 own, float g, const KParams& p) {
   const float dk = (py.x - own.x) + (py.y - own.y);
-  return fmaf(omega, dk, p.oms_f * g);
+  return fmaf(p.omega_f[k], dk, fmaf(p.omega_lo[k], dk, p.oms_f * g));
 }
 
 __device__ __forceinline__ void two_sum_f(float a, float b, float& s, float& e) {
@@ -1103,7 +1104,7 @@ __global__ void __launch_bounds__(256)
     static_for<0, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
       const int idx = node + pull_offset<D, k>(r);
-      b[k] = hilo_b(p.omega_f[k], phisrc[idx], own, gsrc[k * ps + idx], p);
+      b[k] = hilo_b(k, phisrc[idx], own, gsrc[k * ps + idx], p);
     });
     if (r.lo[0] || r.hi[0]) {
       const double phx = static_cast<double>(own.x) + static_cast<double>(own.y);
@@ -1280,7 +1281,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
             constexpr int k = decltype(K)::value;
             constexpr Vec4i c = vel_vec(D, k);
             const PT* sp = c.v[2] == 0 ? s0 : lsrc + ((it + 1 - c.v[2]) % 3) * P2 + sown;
-            b[k] = hilo_b(p.omega_f[k], sp[-c.v[1] * PX - c.v[0]], own,
+            b[k] = hilo_b(k, sp[-c.v[1] * PX - c.v[0]], own,
                           gA[k * ps + node + pull_offset<D, k>(ri)], p);
           });
           if (ri.lo[0] || ri.hi[0]) {
@@ -1374,7 +1375,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
             constexpr Vec4i c = vel_vec(D, k);
             constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
             const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
-            b[k] = hilo_b(p.omega_f[k], lphi[((it - src_it) % 3) * R + rr], me,
+            b[k] = hilo_b(k, lphi[((it - src_it) % 3) * R + rr], me,
                           lg[fuse_slot<HALF, k>(it - src_it) * R + rr], p);
           });
           if (ri.lo[0] || ri.hi[0]) {
