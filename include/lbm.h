@@ -85,12 +85,14 @@ typedef enum {
                              float64 arithmetic                                          */
   LBM_FP32_HILO = 3       /* g_k as in LBM_FP32_SPLIT, phi as an unevaluated pair
                              hi + lo of float32 (the same 8 bytes per node), float32
-                             arithmetic: each population enters as its offset
-                             b_k = f_k - omega_k (phi(x) + dt R) from the node's own
-                             phi, with phi(x - c_k) - phi(x) = (hi' - hi) + (lo' - lo);
-                             the new phi = phi(x) + dt R + sum_k b_k with dt R an
-                             exact float32 pair, by error-free sums (values a wall
-                             scheme sets, and rows on the walls of x_2 .. x_d, use
+                             arithmetic with error-free transformations: each
+                             population enters as its offset b_k = f_k - omega_k
+                             (phi(x) + dt R) from the node's own phi, kept as exact
+                             float32 pieces (phi(x - c_k) - phi(x) as the pair
+                             (hi' - hi, lo' - lo), omega_k and dt R as float32
+                             pairs, products split by fma, sums by TwoSum); the new
+                             phi and g_k are rounded once (values a wall scheme
+                             sets, and rows on the walls of x_2 .. x_d, use
                              float64).  No tapes or batches.                     */
 } lbm_precision;
 

@@ -998,52 +998,112 @@ __device__ __forceinline__ void split_store(const double (&f)[q_of(D)], float* _
 // ---- hi/lo mode: the step in float32 arithmetic.  With b_k = f_k - omega_k
 // (phi(x) + dt R) at the node x being updated (sum_k omega_k = 1):
 //   bulk population, pulled from y = x - c_k:
-//     b_k = omega_k (phi(y) - phi(x)) + (1 - s) g_k(y),
-//     phi(y) - phi(x) = (hi(y) - hi(x)) + (lo(y) - lo(x)), nearly exact for
-//     neighbouring values (Sterbenz);
+//     b_k = omega_k (phi(y) - phi(x)) + (1 - s) g_k(y);
 //   population set by a wall scheme to the value v (float64):
 //     b_k = v - omega_k (phi(x) + dt R);
 //   beta = sum_k b_k, phi_new = phi(x) + dt R + beta, g_new_k = b_k - omega_k beta.
-// dt R enters phi only, as an exact float32 pair added with error-free sums
-// (rounded to float32 it would add the same error every step and drift
-// linearly); the float32 rounding left is that of beta, the transport part
-// of the update.  Every kernel of the mode uses these helpers (two-step
-// passes equal single steps bit for bit); rows on walls of x_2.. go through
-// the float64 split formulas (split_pull / split_store on the pair), in
-// single steps and pairs alike.
-// omega_k enters as the float32 pair omega_f + omega_lo: rounded to float32
-// alone it would perturb the stencil weights the same way every step
-__device__ __forceinline__ float hilo_b(int k, float2 py, float2 own, float g, const KParams& p) {
-  const float dk = (py.x - own.x) + (py.y - own.y);
-  return fmaf(p.omega_f[k], dk, fmaf(p.omega_lo[k], dk, p.oms_f * g));
+// Every quantity is kept free of rounding until g_new_k and phi_new are
+// rounded once: phi(y) - phi(x) as the pair (hi' - hi, lo' - lo) (exact for
+// neighbouring values, Sterbenz), omega_k as the float32 pair omega_f +
+// omega_lo, the product omega_f (hi' - hi) with its exact error (fma), beta
+// as a TwoSum over those products plus the small terms, dt R as an exact
+// float32 pair.  Rounded to float32 on the way, the first-order differences
+// and the weights repeat nearly the same error every step, which then adds
+// up like a bias (measured: 4e-8 drift from float64 after 2000 steps at 512^3,
+// where the split mode drifts 1e-9).  The helpers disable floating-point
+// contraction, which would break the error-free sums.  Every kernel of the
+// mode uses them in the same order (two-step passes equal single steps bit
+// for bit); rows on walls of x_2.. go through the float64 split formulas
+// (split_pull / split_store on the pair), in single steps and pairs alike.
+struct HiloTerm {
+  float p;  // omega_f (hi' - hi), rounded
+  float q;  // (1 - s) g_k(y)
+  float r;  // the error of p plus the small terms
+};
+
+__device__ __forceinline__ HiloTerm hilo_term(int k, float2 py, float2 own, float g,
+                                              const KParams& p) {
+#pragma clang fp contract(off)
+  const float dh = py.x - own.x, dl = py.y - own.y;
+  const float pp = p.omega_f[k] * dh;
+  const float ep = fmaf(p.omega_f[k], dh, -pp);
+  return {pp, p.oms_f * g, fmaf(p.omega_lo[k], dh, fmaf(p.omega_f[k], dl, ep))};
+}
+
+// a b_k given in float64 (wall-set populations)
+__device__ __forceinline__ HiloTerm hilo_term_of(double b) {
+  const float h = static_cast<float>(b);
+  return {h, 0.0f, static_cast<float>(b - static_cast<double>(h))};
 }
 
 __device__ __forceinline__ void two_sum_f(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
   s = a + b;
   const float bp = s - a;
   e = (a - (s - bp)) + (b - bp);
 }
 
+struct HiloAcc {
+  float s = 0.0f, c = 0.0f, q = 0.0f, r = 0.0f;
+};
+
+__device__ __forceinline__ void hilo_add(HiloAcc& acc, const HiloTerm& t) {
+#pragma clang fp contract(off)
+  float e;
+  two_sum_f(acc.s, t.p, acc.s, e);
+  acc.c += e;
+  acc.q += t.q;
+  acc.r += t.r;
+}
+
+// beta as a normalised pair
+__device__ __forceinline__ float2 hilo_beta(const HiloAcc& acc) {
+#pragma clang fp contract(off)
+  const float t = (acc.c + acc.r) + acc.q;
+  const float h = acc.s + t;
+  return make_float2(h, t - (h - acc.s));
+}
+
+// g_new_k = b_k - omega_k beta, rounded once
+__device__ __forceinline__ float hilo_gnew(int k, const HiloTerm& t, float2 beta,
+                                           const KParams& p) {
+#pragma clang fp contract(off)
+  const float m = p.omega_f[k] * beta.x;
+  const float em = fmaf(p.omega_f[k], beta.x, -m);
+  float d, ed;
+  two_sum_f(t.p, -m, d, ed);
+  const float small =
+      fmaf(-p.omega_f[k], beta.y, fmaf(-p.omega_lo[k], beta.x, (ed - em) + t.r));
+  return d + (t.q + small);
+}
+
 // (hi + lo) + (dtR_hi + dtR_lo) + beta as a normalised pair
-__device__ __forceinline__ float2 hilo_advance(float2 v, float beta, const KParams& p) {
+__device__ __forceinline__ float2 hilo_advance(float2 v, float2 beta, const KParams& p) {
+#pragma clang fp contract(off)
   float s1, e1, s2, e2;
   two_sum_f(v.x, p.dtR_hi, s1, e1);
-  two_sum_f(s1, beta, s2, e2);
-  const float lo = ((v.y + p.dtR_lo) + e1) + e2;
+  two_sum_f(s1, beta.x, s2, e2);
+  const float lo = (((v.y + p.dtR_lo) + beta.y) + e1) + e2;
   const float h = s2 + lo;
   return make_float2(h, lo - (h - s2));
 }
 
-template <int D>
-__device__ __forceinline__ void hilo_finish(const float (&b)[q_of(D)], float2 own, float2& phi_new,
-                                            float (&g)[q_of(D)], const KParams& p) {
-  constexpr int Q = q_of(D);
-  float beta = 0.0f;
-#pragma unroll
-  for (int k = 0; k < Q; ++k) beta += b[k];
+// the step of one node from its terms: term(K) gives HiloTerm of population
+// K; it is evaluated twice (beta first, then g_new), and a compiler memory
+// barrier between the passes makes the second pass reload its LDS inputs
+// instead of holding three values per population in registers
+template <int D, class Term>
+__device__ __forceinline__ void hilo_node(Term&& term, float2 own, float2& phi_new,
+                                          float (&g)[q_of(D)], const KParams& p) {
+  HiloAcc acc;
+  static_for<0, q_of(D)>([&](auto K) { hilo_add(acc, term(K)); });
+  const float2 beta = hilo_beta(acc);
   phi_new = hilo_advance(own, beta, p);
-#pragma unroll
-  for (int k = 0; k < Q; ++k) g[k] = fmaf(-p.omega_f[k], beta, b[k]);
+  asm volatile("" ::: "memory");
+  static_for<0, q_of(D)>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    g[k] = hilo_gnew(k, term(K), beta, p);
+  });
 }
 
 template <int D>
@@ -1100,33 +1160,34 @@ __global__ void __launch_bounds__(256)
     col_setup<D>(p, x, r);
     const int node = r.rowbase + x;
     const float2 own = phisrc[node];
-    float b[Q];
+    float2 py[Q];
+    float gy[Q];
     static_for<0, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
       const int idx = node + pull_offset<D, k>(r);
-      b[k] = hilo_b(k, phisrc[idx], own, gsrc[k * ps + idx], p);
+      py[k] = phisrc[idx];
+      gy[k] = gsrc[k * ps + idx];
     });
-    if (r.lo[0] || r.hi[0]) {
-      const double phx = static_cast<double>(own.x) + static_cast<double>(own.y);
-      const double* W = p.xdata + (r.hi[0] ? S * p.rows : 0) + row;
-      static_for<0, Q>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        constexpr int cx = vel_comp(D, k, 0);
-        if constexpr (cx != 0) {
-          if ((cx == 1) ? r.lo[0] : r.hi[0]) {
-            double v = W[(long long)xface_slot(D, k) * p.rows];
-            if (half) {
-              constexpr int kb = opp_index(D, k);
-              v -= split_fstar_val(p.omega[kb], phx, gsrc[kb * ps + node], p);
-            }
-            b[k] = static_cast<float>(v - p.omega[k] * (phx + p.dtR));
+    const double phx = static_cast<double>(own.x) + static_cast<double>(own.y);
+    const double* W = p.xdata + (r.hi[0] ? S * p.rows : 0) + row;
+    auto term = [&](auto K) -> HiloTerm {
+      constexpr int k = decltype(K)::value;
+      constexpr int cx = vel_comp(D, k, 0);
+      if constexpr (cx != 0) {
+        if ((cx == 1) ? r.lo[0] : r.hi[0]) {
+          double v = W[(long long)xface_slot(D, k) * p.rows];
+          if (half) {
+            constexpr int kb = opp_index(D, k);
+            v -= split_fstar_val(p.omega[kb], phx, gsrc[kb * ps + node], p);
           }
+          return hilo_term_of(v - p.omega[k] * (phx + p.dtR));
         }
-      });
-    }
+      }
+      return hilo_term(k, py[k], own, gy[k], p);
+    };
     float2 phi_new;
     float g[Q];
-    hilo_finish<D>(b, own, phi_new, g, p);
+    hilo_node<D>(term, own, phi_new, g, p);
     hilo_put(phidst, node, phi_new);
 #pragma unroll
     for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(g[k], gdst + k * ps + node);
@@ -1276,32 +1337,30 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
         if constexpr (HILO) {
           const float2 own = *s0;
           const double phx = static_cast<double>(own.x) + static_cast<double>(own.y);
-          float b[Q];
+          float gy[Q];
           static_for<0, Q>([&](auto K) {
             constexpr int k = decltype(K)::value;
+            gy[k] = gA[k * ps + node + pull_offset<D, k>(ri)];
+          });
+          const double* W = p.xdata + (ri.hi[0] ? SX * p.rows : 0) + row;
+          auto term = [&](auto K) -> HiloTerm {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                double v = W[(long long)xface_slot(D, k) * p.rows];
+                if (HALF) {
+                  constexpr int kb = opp_index(D, k);
+                  v -= split_fstar_val(p.omega[kb], phx, gA[kb * ps + node], p);
+                }
+                return hilo_term_of(v - p.omega[k] * (phx + p.dtR));
+              }
+            }
             constexpr Vec4i c = vel_vec(D, k);
             const PT* sp = c.v[2] == 0 ? s0 : lsrc + ((it + 1 - c.v[2]) % 3) * P2 + sown;
-            b[k] = hilo_b(k, sp[-c.v[1] * PX - c.v[0]], own,
-                          gA[k * ps + node + pull_offset<D, k>(ri)], p);
-          });
-          if (ri.lo[0] || ri.hi[0]) {
-            const double* W = p.xdata + (ri.hi[0] ? SX * p.rows : 0) + row;
-            static_for<0, Q>([&](auto K) {
-              constexpr int k = decltype(K)::value;
-              constexpr int cx = vel_comp(D, k, 0);
-              if constexpr (cx != 0) {
-                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
-                  double v = W[(long long)xface_slot(D, k) * p.rows];
-                  if (HALF) {
-                    constexpr int kb = opp_index(D, k);
-                    v -= split_fstar_val(p.omega[kb], phx, gA[kb * ps + node], p);
-                  }
-                  b[k] = static_cast<float>(v - p.omega[k] * (phx + p.dtR));
-                }
-              }
-            });
-          }
-          hilo_finish<D>(b, own, phi, g, p);
+            return hilo_term(k, sp[-c.v[1] * PX - c.v[0]], own, gy[k], p);
+          };
+          hilo_node<D>(term, own, phi, g, p);
         } else {
           double f[Q];
           static_for<0, Q>([&](auto K) {
@@ -1369,36 +1428,30 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
         if constexpr (HILO) {
           const float2 me = lphi[((it - 1) % 3) * R + own];
           const double phx = static_cast<double>(me.x) + static_cast<double>(me.y);
-          float b[Q];
-          static_for<0, Q>([&](auto K) {
+          const double* W = xd2 + (ri.hi[0] ? SX * p.rows : 0) + row;
+          auto term = [&](auto K) -> HiloTerm {
             constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
+                double v = W[(long long)xface_slot(D, k) * p.rows];
+                if constexpr (HALF) {
+                  constexpr int kb = opp_index(D, k);
+                  const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
+                  v -= split_fstar_val(p.omega[kb], phx, gb, p);
+                }
+                return hilo_term_of(v - p.omega[k] * (phx + p.dtR));
+              }
+            }
             constexpr Vec4i c = vel_vec(D, k);
             constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
             const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
-            b[k] = hilo_b(k, lphi[((it - src_it) % 3) * R + rr], me,
-                          lg[fuse_slot<HALF, k>(it - src_it) * R + rr], p);
-          });
-          if (ri.lo[0] || ri.hi[0]) {
-            const double* W = xd2 + (ri.hi[0] ? SX * p.rows : 0) + row;
-            static_for<0, Q>([&](auto K) {
-              constexpr int k = decltype(K)::value;
-              constexpr int cx = vel_comp(D, k, 0);
-              if constexpr (cx != 0) {
-                if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
-                  double v = W[(long long)xface_slot(D, k) * p.rows];
-                  if constexpr (HALF) {
-                    constexpr int kb = opp_index(D, k);
-                    const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
-                    v -= split_fstar_val(p.omega[kb], phx, gb, p);
-                  }
-                  b[k] = static_cast<float>(v - p.omega[k] * (phx + p.dtR));
-                }
-              }
-            });
-          }
+            return hilo_term(k, lphi[((it - src_it) % 3) * R + rr], me,
+                             lg[fuse_slot<HALF, k>(it - src_it) * R + rr], p);
+          };
           float2 phi_new;
           float g[Q];
-          hilo_finish<D>(b, me, phi_new, g, p);
+          hilo_node<D>(term, me, phi_new, g, p);
           hilo_put(phiB, node, phi_new);
 #pragma unroll
           for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(g[k], gB + k * ps + node);
