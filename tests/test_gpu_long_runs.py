@@ -199,3 +199,37 @@ def test_d4q33_long_first_axis(bc):
             assert err <= 1e-12, (n, err)
     finally:
         lat.close()
+
+
+# ------------------------------------------------------- precision contract --
+
+def test_split_layouts_hold_the_discretisation_error_at_512():
+    """The benchmark lattice (D3Q19 512^3 full-way, the benchmark field) over
+    200 steps in every storage mode: the float32-split and hi/lo runs stay
+    within a fifth of float64's own discretisation error (relative RMSE against
+    the exact solution) of the float64 run; plain float32 does not, and its
+    drift is printed beside them."""
+    from paper_2410_13165_amd import Lattice
+    w = inputs.BENCH_D3Q19
+    n, steps = w["n"], 200
+    spec = inputs.bench_field()
+    phis, disc = {}, None
+    for precision in ("fp64", "fp32_split", "fp32_hilo", "fp32"):
+        print(f"[contract] {precision} 512^3 x {steps}", flush=True)
+        lat = Lattice(3, (n, n, n), 0.5, dx=1.0 / (n - 1), u=spec["u"], R=spec["R"],
+                      bc=["fullway"] * 3, precision=precision, field=spec)
+        try:
+            lat.step(steps)
+            phis[precision] = lat.phi().clone()
+            if precision == "fp64":
+                dg = lat.diagnostics()
+                disc = dg["rmse"] * math.sqrt(n ** 3) / float(phis["fp64"].norm())
+        finally:
+            lat.close()
+            torch.cuda.empty_cache()
+    ref = phis.pop("fp64")
+    drift = {m: float((p - ref).norm()) / float(ref.norm()) for m, p in phis.items()}
+    print(f"[contract] float64 relative discretisation error {disc:.3e}; drift {drift}", flush=True)
+    assert drift["fp32_split"] < 0.2 * disc
+    assert drift["fp32_hilo"] < 0.2 * disc
+    assert drift["fp32"] > disc
