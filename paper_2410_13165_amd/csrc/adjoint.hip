@@ -249,10 +249,13 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
 #pragma unroll
         for (int k = 0; k < Q; ++k) m += p.omega[k] * static_cast<double>(mu[k]);
         const T ms = static_cast<T>(p.s * m);
+        // the contraction's loads before the stores: the wait for them would
+        // otherwise also wait for the stores, since the vector-memory counter
+        // covers both on this chip
+        if (g2) acc = zdot<D, T>(acc, mu, g2, node, ps, mode, p);
 #pragma unroll
         for (int k = 0; k < Q; ++k)
           __builtin_nontemporal_store(oms * mu[k] + ms, ldst + k * ps + node);
-        if (g2) acc = zdot<D, T>(acc, mu, g2, node, ps, mode, p);
       }
     }
     __syncthreads();

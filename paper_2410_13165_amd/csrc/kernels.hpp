@@ -1257,47 +1257,77 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
     if constexpr (HILO) return v;
     else return split_src(v, p);
   };
-  // the source phi of plane z (zc0 - 2 <= z <= zend + 1) into ring slot
-  // (z - zc0 + 2) mod 3, at (x_1, x_2) = (x0 - 2 + sx, y0 - 2 + sy).  Positions
-  // outside a Dirichlet axis stay unwritten: they are read only by pulls that
-  // the x_1-face data replace (rows on the walls of x_2 / x_3 pull nothing).
-  auto stage = [&](int z) {
-    int gz = z;
-    if (gz < 0 || gz >= n2) {
-      if (p.bc[2] != 0) return;
-      gz = fuse_wrap(gz, n2);
-    }
-    PT* dst = lsrc + ((z - zc0 + 2) % 3) * P2;
-    // the TX interior columns of every row first (aligned wavefront loads),
-    // then the four halo columns
-    for (int t = threadIdx.x; t < P2; t += NT) {
-      int sx, sy;
-      if (t < TX * PY) {
-        sy = t / TX;
-        sx = 2 + t % TX;
-      } else {
-        const int h = t - TX * PY;
-        sy = h >> 2;
-        sx = (h & 3) < 2 ? (h & 3) : TX + (h & 3);
-      }
-      int gx = x0 - 2 + sx, gy = y0 - 2 + sy;
-      if (gx < 0 || gx >= n0) {
-        if (p.bc[0] != 0) continue;
-        gx = fuse_wrap(gx, n0);
-      }
-      if (gy < 0 || gy >= n1) {
-        if (p.bc[1] != 0) continue;
-        gy = fuse_wrap(gy, n1);
-      }
-      dst[sy * PX + sx] = ring_val(phiA[(static_cast<long long>(gz) * n1 + gy) * n0 + gx]);
+  // The source phi of plane z (zc0 - 2 <= z <= zend + 1) goes to ring slot
+  // (z - zc0 + 2) mod 3 at (x_1, x_2) = (x0 - 2 + sx, y0 - 2 + sy): the TX
+  // interior columns of every row first (aligned wavefront loads), then the
+  // four halo columns.  Every thread loads and writes one position in every
+  // iteration, with no branch, so that the compiler's wait for the load is the
+  // one before the ring write and never a wait at the loop head, which would
+  // also wait for the previous iteration's stores.  So threads past the P2
+  // positions repeat those of threads tid - P2 (the same value to the same
+  // LDS word), and positions outside a Dirichlet axis hold the value of the
+  // nearest node inside: they are read only by pulls whose result the x_1-face
+  // data replace (rows on the walls of x_2 / x_3 pull nothing), and planes
+  // outside a Dirichlet x_3 axis or past the chunk are never read.
+  static_assert(P2 <= NT && NT - P2 <= P2, "one or two threads per source-ring position");
+  auto ring_xy = [&](int t, int& sx, int& sy) {
+    if (t < TX * PY) {
+      sy = t / TX;
+      sx = 2 + t % TX;
+    } else {
+      const int h = t - TX * PY;
+      sy = h >> 2;
+      sx = (h & 3) < 2 ? (h & 3) : TX + (h & 3);
     }
   };
-  stage(zc0 - 2);
-  stage(zc0 - 1);
-  stage(zc0);
+  int sx, sy;
+  ring_xy(static_cast<int>(threadIdx.x) < P2 ? static_cast<int>(threadIdx.x)
+                                              : static_cast<int>(threadIdx.x) - P2,
+          sx, sy);
+  auto ring_axis = [&](int i, int n, int a) {
+    if (i >= 0 && i < n) return i;
+    return p.bc[a] != 0 ? min(max(i, 0), n - 1) : fuse_wrap(i, n);
+  };
+  const int sgx = ring_axis(x0 - 2 + sx, n0, 0), sgy = ring_axis(y0 - 2 + sy, n1, 1);
+  const int s_off = sy * PX + sx;
+  auto stage_load = [&](int z) -> PT {
+    const int gz = ring_axis(z, n2, 2);
+    return phiA[(static_cast<long long>(gz) * n1 + sgy) * n0 + sgx];
+  };
+  auto stage_put = [&](int z, PT v) { lsrc[((z - zc0 + 2) % 3) * P2 + s_off] = ring_val(v); };
+  // the hi/lo pass's staging after step 2, positions recomputed per call
+  auto stage_late = [&](int z) {
+    const int gz = ring_axis(z, n2, 2);
+    const int t = threadIdx.x;
+    if (t >= P2) return;
+    int tx, ty;
+    ring_xy(t, tx, ty);
+    const int gx = ring_axis(x0 - 2 + tx, n0, 0), gy = ring_axis(y0 - 2 + ty, n1, 1);
+    lsrc[((z - zc0 + 2) % 3) * P2 + ty * PX + tx] =
+        ring_val(phiA[(static_cast<long long>(gz) * n1 + gy) * n0 + gx]);
+  };
+  {
+    const PT v0 = stage_load(zc0 - 2), v1 = stage_load(zc0 - 1), v2 = stage_load(zc0);
+    stage_put(zc0 - 2, v0);
+    stage_put(zc0 - 1, v1);
+    stage_put(zc0, v2);
+  }
   __syncthreads();
   for (int it = 0; it < iters; ++it) {
     const int zp = zc0 - 1 + it;
+    // The source plane zp + 2 of the next iteration replaces plane zp - 1 (ring
+    // slot it mod 3) after the barrier that ends step 1, the last reader of
+    // that plane.  The split pass loads it here, so that the load is in flight
+    // with step 1's gathers.  Loaded after step 2 instead, the wait for it
+    // before the ring write also waits for all of step 2's stores, since the
+    // vector-memory counter covers stores on this chip: 6.60 against 6.07 ms
+    // per 512^3 launch.  (In the last iteration the plane is loaded and written
+    // but not read.)  The hi/lo pass stages after step 2 (below): its step 1
+    // spills registers, and the value and ring position held through the loop
+    // made it spill more (16.9 and 18.7 ms against 15.7 ms, loaded before and
+    // after step 1).
+    PT nxt{};
+    if constexpr (!HILO) nxt = stage_load(zp + 2);
     // fuse_region order: a wavefront's gathers start on the tile's aligned
     // x_1 origin (measured 7% faster than plain region order at 512^3)
     for (int t = threadIdx.x; t < R; t += NT) {
@@ -1412,6 +1442,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
       lphi[(it % 3) * R + r] = ring_val(phi);
     }
     __syncthreads();
+    if constexpr (!HILO) stage_put(zp + 2, nxt);
     if (it >= 2) {
       const int gz = zp - 1;
       for (int o = threadIdx.x; o < TX * TY; o += NT) {
@@ -1489,9 +1520,9 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
         }
       }
     }
-    // the next iteration's source plane zp + 2 replaces plane zp - 1, which
-    // this iteration's step 1 was the last to read
-    if (it + 1 < iters) stage(zp + 2);
+    if constexpr (HILO) {
+      if (it + 1 < iters) stage_late(zp + 2);
+    }
     __syncthreads();
   }
 }
