@@ -284,6 +284,54 @@ def run_d2q9(n=2048):
     return out
 
 
+def run_d4q33(n=96, steps=32):
+    """Example 3 (Sec. 5) at benchmark size: D4Q33, phi* = sin[pi (sum_i x_i - u_i t)]
+    on [-1, 1]^4 with u = (0.05, 0.2, 0.08, 0.1), tau = 1/2, K = 3, n^4 nodes,
+    periodic and full-way (P = 4), float32 and float64, one step per pass.
+    Reports MLUPS, the bulk kernel's mean launch time (HIP events) and its
+    algorithmic rate, 2 q sizeof(T) bytes per node and step over the rows off
+    the walls of x_2..x_4, and the RMSE against the exact solution."""
+    import torch
+    from paper_2410_13165_amd import Lattice, inputs
+    u = [0.05, 0.2, 0.08, 0.1]
+    spec = inputs.diagonal_sine(4, u)
+    out = {"workload": (f"D4Q33 {n}^4, Example 3 field sin(pi (sum x_i - u_i t)) on [-1,1]^4, "
+                        f"u=(0.05,0.2,0.08,0.1), tau=1/2, K=3, P=4, {steps} steps")}
+    for bc in ("periodic", "fullway"):
+        dx = 2.0 / n if bc == "periodic" else 2.0 / (n - 1)
+        bulk_nodes = n ** 4 if bc == "periodic" else (n - 2) ** 3 * n
+        for prec in ("fp32", "fp64"):
+            lat = Lattice(4, (n,) * 4, 0.5, dx=dx, u=u, origin=[-1.0] * 4, bc=[bc] * 4, P=4,
+                          K=3, precision=prec, field=spec)
+            try:
+                q = lat.info()["q"]
+                lat.step(4)
+                torch.cuda.synchronize()
+                lat.profile_begin(steps)
+                t0 = time.perf_counter()
+                lat.step(steps)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                prof = lat.profile_end()
+                rmse = lat.diagnostics()["rmse"]
+            finally:
+                lat.close()
+                torch.cuda.empty_cache()
+            esize = 8 if prec == "fp64" else 4
+            bulk_s = prof["bulk_ms"] / prof["launches"] / 1e3
+            bulk_bytes = bulk_nodes * 2 * q * esize * prof["steps"] / prof["launches"]
+            rec = {"mlups": round(n ** 4 * steps / sec / 1e6, 1),
+                   "steps_per_launch": prof["steps"] / prof["launches"],
+                   "bulk_ms": round(bulk_s * 1e3, 4),
+                   "bulk_gbs": round(bulk_bytes / bulk_s / 1e9, 1),
+                   "bulk_frac": round(bulk_bytes / bulk_s / 1e9 / HBM_PEAK_GBS, 4),
+                   "rmse": float(f"{rmse:.4g}")}
+            out[f"{bc}_{prec}"] = rec
+            print(f"# d4q33 {bc} {prec}: {rec['mlups']:.0f} MLUPS, bulk {rec['bulk_gbs']:.0f} GB/s"
+                  f", rmse {rmse:.3e}", file=sys.stderr, flush=True)
+    return out
+
+
 def run_d2q9_convergence(sizes=(64, 128, 256, 512, 1024, 2048)):
     """The grid-refinement study of the D2Q9 plane wave: phi0 = sin(2 pi x)
     sin(2 pi y), u = (0.1, 0.2), periodic unit square, n^2 nodes and n steps
@@ -486,6 +534,7 @@ def main(argv=None):
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-fixed-error", action="store_true")
     ap.add_argument("--no-d2q9", action="store_true")
+    ap.add_argument("--no-d4q33", action="store_true")
     ap.add_argument("--no-halfway", action="store_true")
     ap.add_argument("--halfway-steps", type=int, default=200)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -576,6 +625,7 @@ def main(argv=None):
                   f"rmse {r['rmse']:.3e}", file=sys.stderr, flush=True)
     d2q9 = None if args.no_d2q9 else run_d2q9()
     conv = None if args.no_d2q9 else run_d2q9_convergence()
+    d4q33 = None if args.no_d4q33 else run_d4q33()
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep()
@@ -666,6 +716,7 @@ def main(argv=None):
         "halfway": halfway,
         "d2q9": d2q9,
         "d2q9_convergence": conv,
+        "d4q33": d4q33,
         "sweep": sweep,
         "adjoint_fwd_ratio": round(adj["ratio"], 4) if adj else None,
         "adjoint": ({k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in adj.items()}

@@ -32,8 +32,22 @@ FLAGS = [
 ]
 
 
+# The d = 4 wall kernels unroll over the 33 populations of D4Q33 and index the
+# field table of their by-value parameter block by mode at run time. The
+# front end first copies that block (3184 B) to private memory, and LLVM's
+# InstCombine turns the copy back into reads of the kernel-argument segment
+# only while the copy has at most 300 users (its default); past that, every
+# thread copied the block to scratch at launch (4.5 KB of scratch per lane).
+# The limit is raised for those translation units only.
+SOURCE_FLAGS = {
+    "walls_d4.hip": ["-mllvm", "-instcombine-max-copied-from-constant-users=4000"],
+    "walls_d4t.hip": ["-mllvm", "-instcombine-max-copied-from-constant-users=4000"],
+}
+
+
 def compile_command(src: str, obj: str) -> list[str]:
-    return [hipcc()] + FLAGS + ["-c", "-o", obj, os.path.join(CSRC, src)]
+    return ([hipcc()] + FLAGS + SOURCE_FLAGS.get(src, [])
+            + ["-c", "-o", obj, os.path.join(CSRC, src)])
 
 
 def link_command(objs: list[str], out: str = LIB) -> list[str]:

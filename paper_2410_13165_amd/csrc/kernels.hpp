@@ -254,11 +254,14 @@ inline int wall_variant(const KParams& p) {
 // equation: c_k . grad F = alpha . grad_tan F + beta d_t F with
 // alpha = c_k - (c_kj / u_j) u (tangential, alpha_j = 0) and beta = -c_kj / u_j,
 // i.e. the factor alpha . kappa + beta (-kappa . u).
-template <int D, bool TAN, int V, class Sel, class Axis>
+//
+// Only the populations K0 <= k < K1 are evaluated (callers split the 33 of
+// D4Q33 into groups, so that fewer sums are live across the mode loop); each
+// val[k] is the same sum over the modes in the same order whatever the group.
+template <int D, bool TAN, int V, int K0 = 0, int K1 = q_of(D), class Sel, class Axis>
 __device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x)[kMaxDim],
                                               double t_n, Sel sel, Axis axis,
                                               double (&val)[q_of(D)]) {
-  constexpr int Q = q_of(D);
   const FieldDev& F = p.field;
   const double dt = p.dt;
   const bool full = wall_full<V>(p);
@@ -269,7 +272,7 @@ __device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x
   const double dt2 = dt * dt, dt3 = dt2 * dt;
   const double t = full ? t_n + dt : t_n;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) val[k] = 0.0;
+  for (int k = K0; k < K1; ++k) val[k] = 0.0;
 #pragma unroll 1
   for (int j = 0; j < F.nmodes; ++j) {
     double ph = 0.0;
@@ -282,7 +285,7 @@ __device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x
       E = exp(ph);
     const double amp = F.amp[j];
     const double w = -F.ku[j];
-    static_for<0, Q>([&](auto K) {
+    static_for<K0, K1>([&](auto K) {
       constexpr int k = decltype(K)::value;
       constexpr Vec4i c = vel_vec(D, k);
       if (!sel(k)) return;
@@ -341,7 +344,7 @@ __device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x
       }
     });
   }
-  static_for<0, Q>([&](auto K) {
+  static_for<K0, K1>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if (!sel(k)) return;
     if (full) {
@@ -384,16 +387,23 @@ __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, c
     constexpr int k = decltype(K)::value;
     ax[k] = TAN ? wall_axis<D, k>(r) : 0;
   });
-  double val[q_of(D)];
-  wall_analytic<D, TAN, V>(p, x, t_n, [&](int k) { return out[k]; },
-                           [&](int k) { return ax[k]; }, val);
   const bool half = !wall_full<V>(p);
-  static_for<0, q_of(D)>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    if (!out[k]) return;
-    double v = val[k];
-    if (half) v -= fstar_local(opp_index(D, k));
-    f[k] = static_cast<A>(v - p.omega[k] * ref);
+  // D4Q33 in three groups of populations (each recomputes the modes' sincos):
+  // its 33 sums held at once left the wall kernels at 256 VGPRs with spills
+  constexpr int G = D == 4 ? 11 : q_of(D);
+  static_for<0, (q_of(D) + G - 1) / G>([&](auto Gi) {
+    constexpr int k0 = decltype(Gi)::value * G;
+    constexpr int k1 = k0 + G < q_of(D) ? k0 + G : q_of(D);
+    double val[q_of(D)];
+    wall_analytic<D, TAN, V, k0, k1>(p, x, t_n, [&](int k) { return out[k]; },
+                                     [&](int k) { return ax[k]; }, val);
+    static_for<k0, k1>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      if (!out[k]) return;
+      double v = val[k];
+      if (half) v -= fstar_local(opp_index(D, k));
+      f[k] = static_cast<A>(v - p.omega[k] * ref);
+    });
   });
 }
 
