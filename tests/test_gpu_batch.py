@@ -52,11 +52,6 @@ def test_batch_matches_oracle_per_instance(precision, tol, K):
             assert rel_l2(got, run.phi()) <= tol, (i, sp)
 
 
-@pytest.mark.skip(reason="runs lbm_batch_tune with the ordered-queue persistent form, which "
-                         "stalled inside the tuner on MI355X twice (once with time-only wait "
-                         "bounds, once with poll bounds and system-scope counters) with no cause "
-                         "found by reading; that form is switched off, so this test stays off "
-                         "the GPU")
 def test_tuner_restores_state_and_configs_agree():
     """Every block shape gives bitwise identical states; tuning leaves the
     state where it was."""
@@ -237,11 +232,6 @@ def test_sweep_workload_persistent_full_size():
             assert rel_l2(got, run.phi()) <= 2e-5, (i, sp)
 
 
-@pytest.mark.skip(reason="runs lbm_batch_tune with the ordered-queue persistent form, which "
-                         "stalled inside the tuner on MI355X twice (once with time-only wait "
-                         "bounds, once with poll bounds and system-scope counters) with no cause "
-                         "found by reading; that form is switched off, so this test stays off "
-                         "the GPU")
 def test_tuner_covers_launch_forms_and_caches(tmp_path, monkeypatch):
     """The tuner times the launches the steps use (launch form and rows per
     tile of the two-step passes), reports the one it keeps, and serves the same
@@ -258,7 +248,7 @@ def test_tuner_covers_launch_forms_and_caches(tmp_path, monkeypatch):
         b.set_initial(phi0)
         cfg = b.tune(4)
         print("[batch] tuned", cfg, flush=True)
-        assert cfg["form"] in ("per_pair", "persistent") and 8 <= cfg["ychunk"] <= 64
+        assert cfg["form"] in ("per_pair", "resident") and 8 <= cfg["ychunk"] <= 64
         assert not cfg["cached"]
         again = b.tune(4)
         assert again["cached"] and again["form"] == cfg["form"] and again["ychunk"] == cfg["ychunk"]
