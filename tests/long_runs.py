@@ -21,15 +21,15 @@ GOLDEN = "long_runs.npz"
 # 64^3 grid and at 200 steps on 128^3; the half-way variant at u = 1e-3 (1,1,1),
 # where that scheme is stable.
 CUBES = {
-    "c3_fullway_64": {"n": 64, "bc": "fullway", "u": [0.05, 0.1, 0.08], "steps": 2000},
-    "c3_fullway_128": {"n": 128, "bc": "fullway", "u": [0.05, 0.1, 0.08], "steps": 200},
-    "c3_halfway_64": {"n": 64, "bc": "halfway", "u": [1e-3, 1e-3, 1e-3], "steps": 2000},
+    "d3q19_fullway_64": {"n": 64, "bc": "fullway", "u": [0.05, 0.1, 0.08], "steps": 2000},
+    "d3q19_fullway_128": {"n": 128, "bc": "fullway", "u": [0.05, 0.1, 0.08], "steps": 200},
+    "d3q19_halfway_64": {"n": 64, "bc": "halfway", "u": [1e-3, 1e-3, 1e-3], "steps": 2000},
 }
 
 # The gradient workload's forward run (D3Q19 periodic, Gaussian random field of
 # correlation length 0.1, seed 5, u = (0.05, 0.1, 0.08), tau = 1/2, K = 3 with
 # fourth-order finite-difference gradients) at its 1000 steps on a 32^3 grid.
-GRF = {"c5_grf_32": {"n": 32, "steps": 1000}}
+GRF = {"d3q19_grf_32": {"n": 32, "steps": 1000}}
 
 # D2Q9 stability sweep: the first four instances of each grid size, in the
 # order of inputs.sweep_specs(), over the sweep's 4000 steps.

@@ -66,7 +66,7 @@ def _compare(golden, name, phi_or, diag, precision, steps):
     assert diag["nonfinite"] == 0
 
 
-# ------------------------------------------------------------------ C1 ------
+# ------------------------------------ D1Q3 plane wave, 256 nodes, 1000 steps ------
 
 @pytest.mark.parametrize("tau", [0.5, 0.8])
 def test_d1q3_plane_wave_1000_steps(tau):
@@ -95,13 +95,13 @@ def test_d1q3_plane_wave_1000_steps(tau):
         assert 1e-2 < dg["rmse"] < 1e-1  # tau != 1/2 is first order
 
 
-# ------------------------------------------------------------------ C3 ------
+# ------------------- D3Q19 Dirichlet cubes, 64^3 x 2000 and 128^3 x 200 steps ------
 
-CUBE_CASES = [("c3_fullway_64", "fp64"), ("c3_fullway_64", "fp32_split"),
-              ("c3_fullway_64", "fp32"), ("c3_fullway_128", "fp64"),
-              ("c3_fullway_128", "fp32_split"), ("c3_fullway_128", "fp32"),
-              ("c3_halfway_64", "fp64"), ("c3_halfway_64", "fp32_split"),
-              ("c3_fullway_64", "fp32_hilo"), ("c3_halfway_64", "fp32_hilo")]
+CUBE_CASES = [("d3q19_fullway_64", "fp64"), ("d3q19_fullway_64", "fp32_split"),
+              ("d3q19_fullway_64", "fp32"), ("d3q19_fullway_128", "fp64"),
+              ("d3q19_fullway_128", "fp32_split"), ("d3q19_fullway_128", "fp32"),
+              ("d3q19_halfway_64", "fp64"), ("d3q19_halfway_64", "fp32_split"),
+              ("d3q19_fullway_64", "fp32_hilo"), ("d3q19_halfway_64", "fp32_hilo")]
 
 
 @pytest.mark.parametrize("name,precision", CUBE_CASES)
@@ -118,13 +118,13 @@ def test_dirichlet_cube_full_length(golden, name, precision):
     _compare(golden, name, phi, dg, precision, c["steps"])
 
 
-# ------------------------------------------------------------------ C5 ------
+# ------------------ D3Q19 periodic Gaussian random field, 32^3 x 1000 steps ------
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split", "fp32_hilo", "fp32"])
 def test_gaussian_field_forward_full_length(golden, precision):
     """The gradient workload's forward run (periodic, Gaussian random field,
     finite-difference initial gradient) at its 1000 steps on 32^3."""
-    name = "c5_grf_32"
+    name = "d3q19_grf_32"
     g = LR.grf_problem(name)
     print(f"[long] {name} {precision}", flush=True)
     lat = gpu_lattice(3, g["dims"], g["dx"], None, u=g["u"], precision=precision)
@@ -138,7 +138,7 @@ def test_gaussian_field_forward_full_length(golden, precision):
     _compare(golden, name, phi, dg, precision, g["steps"])
 
 
-# ------------------------------------------------------------------ C4 ------
+# ------------------ D2Q9 stability-sweep subset, 64^2..512^2 x 4000 steps ------
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_sweep_subset_4000_steps(golden, precision):
