@@ -616,7 +616,7 @@ def main(argv=None):
         halfway = {"workload": (f"D3Q19 {args.n}^3 half-way Dirichlet on all faces, same "
                                 "cosines, u=(1e-3,1e-3,1e-3), R=1, tau=1/2, K=3, P=4, "
                                 f"{args.halfway_steps} steps")}
-        for m in ("fp32", "fp64"):
+        for m in ("fp32", "fp64", "fp32_split"):
             r = run_mode(m, args.halfway_steps, 4, args.n, scheme="halfway", u=[1e-3] * 3)
             halfway[m] = {"mlups": round(r["mlups"], 1), "bulk_gbs": round(r["bulk_gbs"], 1),
                           "steps_per_launch": r["steps_per_launch"],

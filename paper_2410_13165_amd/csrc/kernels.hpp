@@ -1216,24 +1216,26 @@ __global__ void __launch_bounds__(256)
 // plane.  Gathered from global memory instead, every source plane is read 19
 // times per node over three iterations, more than the L2 of an XCD holds
 // (measured: 1.67x the algorithmic reads of the pass, 1.17x with the ring).
+//
+// With half-way x_1 walls an x_1-face node of output plane z - 1 also needs its
+// own step-1 g of every kbar opposite an unknown; of these only kbar =
+// (-+1, 0, -1) has c_3 = -1, whose single slot the next plane overwrites, so a
+// side buffer keeps that one value per face node (two faces x (TY + 2) rows x
+// two plane parities), as in the forward pass, and the tile is the full-way one.
 template <bool HALF>
-struct FuseSplitShape;
-template <>
-struct FuseSplitShape<false> {
+struct FuseSplitShape {
   static constexpr int TX = 64, TY = 10, NT = 1024, SLOTS = 38;
-};
-template <>
-struct FuseSplitShape<true> {
-  static constexpr int TX = 64, TY = 9, NT = 1024, SLOTS = 43;
+  static constexpr int SIDE = HALF ? 4 * (TY + 2) : 0;
 };
 
-// bytes of LDS of a split pass: g slots, the step-1 phi ring, the source phi ring
+// bytes of LDS of a split pass: g slots, the step-1 phi ring, the source phi
+// ring, the half-way side buffer
 template <bool HALF>
 constexpr size_t fuse_split_lds() {
   using S = FuseSplitShape<HALF>;
   return sizeof(float) * S::SLOTS * (S::TX + 2) * (S::TY + 2) +
          sizeof(double) * 3 * (S::TX + 2) * (S::TY + 2) +
-         sizeof(double) * 3 * (S::TX + 4) * (S::TY + 4);
+         sizeof(double) * 3 * (S::TX + 4) * (S::TY + 4) + sizeof(float) * S::SIDE;
 }
 
 // HILO: the hi/lo mode, whose rings hold the (hi, lo) pairs of phi instead of t.
@@ -1255,6 +1257,8 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
   float* lg = reinterpret_cast<float*>(fuse_lds);
   PT* lphi = reinterpret_cast<PT*>(fuse_lds + sizeof(float) * S::SLOTS * R);
   PT* lsrc = lphi + 3 * R;
+  // half-way only: side[((parity * 2) + face) * RY + ry]
+  float* side = reinterpret_cast<float*>(lsrc + 3 * P2);
   const long long ps = p.pstride;
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
   int tx_, ty_, tz_;
@@ -1402,13 +1406,23 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
           };
           hilo_node<D>(term, own, phi, g, p);
         } else {
+          // all 19 gathers issued before any is used: at its register limit
+          // the half-way pass otherwise took them one to four at a time, each
+          // followed by a wait for all outstanding loads (10.6 ms per 512^3
+          // launch against 5.8 ms full-way)
+          float gy[Q];
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            gy[k] = gA[k * ps + node + pull_offset<D, k>(ri)];
+          });
+          asm volatile("" ::: "memory");
           double f[Q];
           static_for<0, Q>([&](auto K) {
             constexpr int k = decltype(K)::value;
             constexpr Vec4i c = vel_vec(D, k);
             const PT* sp = c.v[2] == 0 ? s0 : lsrc + ((it + 1 - c.v[2]) % 3) * P2 + sown;
             const double ph = sp[-c.v[1] * PX - c.v[0]];
-            f[k] = split_fstar_t(p.omega[k], ph, gA[k * ps + node + pull_offset<D, k>(ri)], p);
+            f[k] = split_fstar_t(p.omega[k], ph, gy[k], p);
           });
           if (ri.lo[0] || ri.hi[0]) {
             const double* W = p.xdata + (ri.hi[0] ? SX * p.rows : 0) + row;
@@ -1447,9 +1461,23 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
       }
       static_for<0, Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
-        lg[fuse_slot<HALF, k>(it) * R + r] = g[k];
+        lg[fuse_slot<false, k>(it) * R + r] = g[k];
       });
       lphi[(it % 3) * R + r] = ring_val(phi);
+      if constexpr (HALF) {
+        if (!ri.rowwall && (ri.lo[0] || ri.hi[0])) {
+          // g of kbar = (-+1, 0, -1) opposite the face's unknown (+-1, 0, +1),
+          // for step 2 of this plane (read one iteration later)
+          static_for<0, Q>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int cx = vel_comp(D, k, 0);
+            if constexpr (cx != 0 && vel_comp(D, k, 2) == 1) {
+              if ((cx == 1) ? ri.lo[0] : ri.hi[0])
+                side[((it & 1) * 2 + (cx == 1 ? 0 : 1)) * RY + ry] = g[opp_index(D, k)];
+            }
+          });
+        }
+      }
     }
     __syncthreads();
     if constexpr (!HILO) stage_put(zp + 2, nxt);
@@ -1466,6 +1494,15 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
         col_setup<D>(p, gx, ri);
         const int node = ri.rowbase + gx;
         const int own = (oy + 1) * RX + (ox + 1);
+        // the node's own step-1 g of kbar (half-way faces): the side buffer for
+        // c_3(kbar) = -1, whose slot the current plane has overwritten
+        auto own_g = [&](auto KB, int cx) -> float {
+          constexpr int kb = decltype(KB)::value;
+          if constexpr (vel_comp(D, kb, 2) == -1)
+            return side[(((it - 1) & 1) * 2 + (cx == 1 ? 0 : 1)) * RY + oy + 1];
+          else
+            return lg[fuse_slot<false, kb>(it - 1) * R + own];
+        };
         if constexpr (HILO) {
           const float2 me = lphi[((it - 1) % 3) * R + own];
           const double phx = static_cast<double>(me.x) + static_cast<double>(me.y);
@@ -1478,7 +1515,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
                 double v = W[(long long)xface_slot(D, k) * p.rows];
                 if constexpr (HALF) {
                   constexpr int kb = opp_index(D, k);
-                  const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
+                  const float gb = own_g(std::integral_constant<int, kb>{}, cx);
                   v -= split_fstar_val(p.omega[kb], phx, gb, p);
                 }
                 return hilo_term_of(v - p.omega[k] * (phx + p.dtR));
@@ -1488,7 +1525,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
             constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
             const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
             return hilo_term(k, lphi[((it - src_it) % 3) * R + rr], me,
-                             lg[fuse_slot<HALF, k>(it - src_it) * R + rr], p);
+                             lg[fuse_slot<false, k>(it - src_it) * R + rr], p);
           };
           float2 phi_new;
           float g[Q];
@@ -1504,7 +1541,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
             constexpr int src_it = c.v[2] == 0 ? 1 : (c.v[2] == 1 ? 2 : 0);
             const int rr = (oy + 1 - c.v[1]) * RX + (ox + 1 - c.v[0]);
             const double ph = lphi[((it - src_it) % 3) * R + rr];
-            const float gk = lg[fuse_slot<HALF, k>(it - src_it) * R + rr];
+            const float gk = lg[fuse_slot<false, k>(it - src_it) * R + rr];
             f[k] = split_fstar_t(p.omega[k], ph, gk, p);
           });
           if (ri.lo[0] || ri.hi[0]) {
@@ -1518,7 +1555,7 @@ __global__ void __launch_bounds__((FuseSplitShape<HALF>::NT))
                   if constexpr (HALF) {
                     constexpr int kb = opp_index(D, k);
                     const double ph = lphi[((it - 1) % 3) * R + own];
-                    const float gb = lg[fuse_slot<HALF, kb>(it - 1) * R + own];
+                    const float gb = own_g(std::integral_constant<int, kb>{}, cx);
                     v -= split_fstar_t(p.omega[kb], ph, gb, p);
                   }
                   f[k] = v;
