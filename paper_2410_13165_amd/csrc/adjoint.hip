@@ -63,23 +63,15 @@ __device__ __forceinline__ void block_sum(double v, double* sh, double* out,
 }
 
 // acc + <mu, (omega 1^T - I) f^n> at one node, f^n recovered from the stored
-// forward state g (post-collision, or the split g_k = f_k - omega_k phi):
-// zload reads the node's g, zacc does the arithmetic, zdot both.
+// forward state g (post-collision, or the split g_k = f_k - omega_k phi).
 template <int D, class T>
-__device__ __forceinline__ void zload(const T* __restrict__ g, int node, long long ps,
-                                      T (&gv)[q_of(D)]) {
-#pragma unroll
-  for (int k = 0; k < q_of(D); ++k) gv[k] = g[k * ps + node];
-}
-
-template <int D, class T>
-__device__ __forceinline__ double zacc(double acc, const T (&mu)[q_of(D)],
-                                       const T (&gv)[q_of(D)], int mode, const KParams& p) {
+__device__ __forceinline__ double zdot(double acc, const T (&mu)[q_of(D)], const T* __restrict__ g,
+                                       int node, long long ps, int mode, const KParams& p) {
   constexpr int Q = q_of(D);
   double z[Q];
   if (mode == kSplit) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) z[k] = -static_cast<double>(gv[k]);
+    for (int k = 0; k < Q; ++k) z[k] = -static_cast<double>(g[k * ps + node]);
   } else {
     // omega_k phi + dt omega_k R - g_k with phi = sum_j g_j - dt R, which is
     // omega_k sum_j g_j - g_k; the same form holds for the float32
@@ -88,7 +80,7 @@ __device__ __forceinline__ double zacc(double acc, const T (&mu)[q_of(D)],
     double sum = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      gk[k] = static_cast<double>(gv[k]);
+      gk[k] = static_cast<double>(g[k * ps + node]);
       sum += gk[k];
     }
 #pragma unroll
@@ -97,14 +89,6 @@ __device__ __forceinline__ double zacc(double acc, const T (&mu)[q_of(D)],
 #pragma unroll
   for (int k = 0; k < Q; ++k) acc += static_cast<double>(mu[k]) * z[k];
   return acc;
-}
-
-template <int D, class T>
-__device__ __forceinline__ double zdot(double acc, const T (&mu)[q_of(D)], const T* __restrict__ g,
-                                       int node, long long ps, int mode, const KParams& p) {
-  T gv[q_of(D)];
-  zload<D, T>(g, node, ps, gv);
-  return zacc<D, T>(acc, mu, gv, mode, p);
 }
 
 }  // namespace
@@ -212,12 +196,6 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
         constexpr int k = decltype(K)::value;
         mu[k] = lsrc[k * ps + node + push_offset<D, k>(nb)];
       });
-      // the contraction's loads in flight with the gathers, not after them
-      const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
-                       y0 - 1 + ry < n1 && zp >= zc0 && zp < zend;
-      const bool zd = g1 && own;
-      T gv[Q];
-      if (zd) zload<D, T>(g1, node, ps, gv);
       static_for<0, Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if (leaves<D, k>(nb)) {
@@ -229,7 +207,9 @@ __global__ void __launch_bounds__((FuseShape<T, HALF>::NT))
 #pragma unroll
       for (int k = 0; k < Q; ++k) m += p.omega[k] * static_cast<double>(mu[k]);
       const T ms = static_cast<T>(p.s * m);
-      if (zd) acc = zacc<D, T>(acc, mu, gv, mode, p);
+      const bool own = rx >= 1 && rx <= TX && ry >= 1 && ry <= TY && x0 - 1 + rx < n0 &&
+                       y0 - 1 + ry < n1 && zp >= zc0 && zp < zend;
+      if (g1 && own) acc = zdot<D, T>(acc, mu, g1, node, ps, mode, p);
       static_for<0, Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
         lds[adj_slot<HALF, k>(it) * R + r] = oms * mu[k] + ms;

@@ -388,12 +388,18 @@ __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, c
     ax[k] = TAN ? wall_axis<D, k>(r) : 0;
   });
   const bool half = !wall_full<V>(p);
-  // D4Q33 in three groups of populations (each recomputes the modes' sincos):
-  // its 33 sums held at once left the wall kernels at 256 VGPRs with spills
-  constexpr int G = D == 4 ? 11 : q_of(D);
+  // D4Q33 one population at a time, skipping those that enter from inside
+  // (each evaluated one recomputes the modes' sincos): its 33 sums and their
+  // coefficients held at once left the wall kernels at 256 VGPRs with spills
+  constexpr int G = D == 4 ? 1 : q_of(D);
   static_for<0, (q_of(D) + G - 1) / G>([&](auto Gi) {
     constexpr int k0 = decltype(Gi)::value * G;
     constexpr int k1 = k0 + G < q_of(D) ? k0 + G : q_of(D);
+    if constexpr (G < q_of(D)) {
+      bool any = false;
+      static_for<k0, k1>([&](auto K) { any = any || out[decltype(K)::value]; });
+      if (!any) return;
+    }
     double val[q_of(D)];
     wall_analytic<D, TAN, V, k0, k1>(p, x, t_n, [&](int k) { return out[k]; },
                                      [&](int k) { return ax[k]; }, val);
@@ -1617,7 +1623,7 @@ __global__ void __launch_bounds__(256)
   const long long ps = p.pstride;
   // reference of the float32 deviations at t_{n+1}
   const double ref = kF32 ? p.phi_ref + p.R * (t_n + p.dt) : 0.0;
-  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+  auto update = [&](int x) {
     col_setup<D>(p, x, r);
     const int node = r.rowbase + x;
     T f[Q];
@@ -1629,6 +1635,15 @@ __global__ void __launch_bounds__(256)
       return static_cast<double>(src[kb * ps + node]) + p.omega[kb] * ref;
     });
     collide_store<D, T>(f, dst, ps, node, p);
+  };
+  if constexpr (D == 4) {
+    // one node per thread, the grid's y over x_1 chunks: in a loop over the
+    // row the compiler kept the wall formula's constants of all 33
+    // populations live (256 VGPRs, one wavefront per SIMD)
+    const int x = blockIdx.y * blockDim.x + threadIdx.x;
+    if (x < p.n[0]) update(x);
+  } else {
+    for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) update(x);
   }
 }
 
@@ -1644,7 +1659,7 @@ __global__ void __launch_bounds__(256)
   RowInfo<D> r;
   row_setup<D>(p, row, r);
   const long long ps = p.pstride;
-  for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) {
+  auto update = [&](int x) {
     col_setup<D>(p, x, r);
     const int node = r.rowbase + x;
     double f[Q];
@@ -1653,6 +1668,12 @@ __global__ void __launch_bounds__(256)
       return split_fstar<D>(gsrc, phisrc, ps, node, kb, p);
     });
     split_store<D>(f, gdst, phidst, ps, node, p);
+  };
+  if constexpr (D == 4) {
+    const int x = blockIdx.y * blockDim.x + threadIdx.x;  // as in k_wall
+    if (x < p.n[0]) update(x);
+  } else {
+    for (int x = threadIdx.x; x < p.n[0]; x += blockDim.x) update(x);
   }
 }
 

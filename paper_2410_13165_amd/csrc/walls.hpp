@@ -27,9 +27,17 @@ void launch_xface(unsigned blocks, hipStream_t stream, T* buf, const KParams& p,
   }
 }
 
+// The d = 4 wall kernels take one node per thread: the grid's y covers the x_1
+// chunks of blockDim.x nodes.
+inline dim3 wall_grid(int D, dim3 g, dim3 b, const KParams& p) {
+  if (D == 4) g.y = static_cast<unsigned>((p.n[0] + b.x - 1) / b.x);
+  return g;
+}
+
 template <int D, class T, bool TAN>
 void launch_wall(dim3 g, dim3 b, hipStream_t stream, const T* src, T* dst, const KParams& p,
                  double t) {
+  g = wall_grid(D, g, b, p);
   if constexpr (D == 1 || D == 4) {
     hipLaunchKernelGGL((k_wall<D, T, TAN, -1>), g, b, 0, stream, src, dst, p, t);
   } else {
@@ -46,6 +54,7 @@ void launch_wall(dim3 g, dim3 b, hipStream_t stream, const T* src, T* dst, const
 template <int D, bool TAN, class PT>
 void launch_wall_split(dim3 g, dim3 b, hipStream_t stream, const float* gs, float* gd,
                        const PT* ps, PT* pd, const KParams& p, double t) {
+  g = wall_grid(D, g, b, p);
   if constexpr (D == 1 || D == 4) {
     hipLaunchKernelGGL((k_wall_split<D, TAN, -1, PT>), g, b, 0, stream, gs, gd, ps, pd, p, t);
   } else {
