@@ -27,10 +27,10 @@ void launch_xface(unsigned blocks, hipStream_t stream, T* buf, const KParams& p,
   }
 }
 
-// The d = 4 wall kernels take one node per thread: the grid's y covers the x_1
-// chunks of blockDim.x nodes.
+// The wall kernels of d >= 3 take one node per thread: the grid's y covers the
+// x_1 chunks of blockDim.x nodes.
 inline dim3 wall_grid(int D, dim3 g, dim3 b, const KParams& p) {
-  if (D == 4) g.y = static_cast<unsigned>((p.n[0] + b.x - 1) / b.x);
+  if (D >= 3) g.y = static_cast<unsigned>((p.n[0] + b.x - 1) / b.x);
   return g;
 }
 
