@@ -99,6 +99,16 @@ def test_mixed_periodic_and_dirichlet_axes(scheme):
 
 
 @pytest.mark.parametrize("scheme", ["fullway", "halfway"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_dirichlet_rows_longer_than_a_block(scheme, precision):
+    """300 nodes along x_1: the wall-row kernels of d >= 3 take one node per
+    thread, in a full chunk of 256 and a ragged one of 44; the two-step passes
+    span five x_1 tiles, the last ragged."""
+    spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0, seed=43, kmax=1.0)
+    _check_pair(3, (300, 9, 8), 1.0 / 299, spec, 12, bc=[scheme] * 3, precision=precision)
+
+
+@pytest.mark.parametrize("scheme", ["fullway", "halfway"])
 @pytest.mark.parametrize("precision", ["fp32", "fp32_split", "fp32_hilo"])
 def test_dirichlet_reduced_precision(scheme, precision):
     spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0, seed=41, kmax=1.0)
