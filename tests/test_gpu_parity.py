@@ -415,7 +415,8 @@ def test_zero_steps_and_error_reporting():
 
 @pytest.mark.parametrize("precision,scheme", [("fp32", "fullway"), ("fp64", "fullway"),
                                               ("fp32_split", "fullway"), ("fp32_hilo", "fullway"),
-                                              ("fp32", "halfway"), ("fp64", "halfway")])
+                                              ("fp32", "halfway"), ("fp64", "halfway"),
+                                              ("fp32_split", "halfway"), ("fp32_hilo", "halfway")])
 def test_benchmark_configuration_sampled(precision, scheme):
     """D3Q19, 512^3 nodes, full-way (the benchmark) or half-way walls on all
     faces, in the benchmark's launch configuration (a two-step pass, then one
