@@ -32,14 +32,16 @@ FLAGS = [
 ]
 
 
-# The d = 4 wall kernels unroll over the 33 populations of D4Q33 and index the
-# field table of their by-value parameter block by mode at run time. The
-# front end first copies that block (3184 B) to private memory, and LLVM's
-# InstCombine turns the copy back into reads of the kernel-argument segment
-# only while the copy has at most 300 users (its default); past that, every
-# thread copied the block to scratch at launch (4.5 KB of scratch per lane).
-# The limit is raised for those translation units only.
+# The wall kernels of d = 3 and 4 unroll over the populations (19 of D3Q19, 33
+# of D4Q33) and index the field table of their by-value parameter block by mode
+# at run time. The front end first copies that block (3184 B) to private
+# memory, and LLVM's InstCombine turns the copy back into reads of the
+# kernel-argument segment only while the copy has at most 300 users (its
+# default); past that, every thread copied the block to scratch at launch (4.5
+# KB of scratch per lane). The limit is raised for those translation units only.
 SOURCE_FLAGS = {
+    "walls_d3.hip": ["-mllvm", "-instcombine-max-copied-from-constant-users=4000"],
+    "walls_d3t.hip": ["-mllvm", "-instcombine-max-copied-from-constant-users=4000"],
     "walls_d4.hip": ["-mllvm", "-instcombine-max-copied-from-constant-users=4000"],
     "walls_d4t.hip": ["-mllvm", "-instcombine-max-copied-from-constant-users=4000"],
 }

@@ -255,107 +255,130 @@ inline int wall_variant(const KParams& p) {
 // alpha = c_k - (c_kj / u_j) u (tangential, alpha_j = 0) and beta = -c_kj / u_j,
 // i.e. the factor alpha . kappa + beta (-kappa . u).
 //
-// Only the populations K0 <= k < K1 are evaluated (callers split the 33 of
-// D4Q33 into groups, so that fewer sums are live across the mode loop); each
-// val[k] is the same sum over the modes in the same order whatever the group.
-template <int D, bool TAN, int V, int K0 = 0, int K1 = q_of(D), class Sel, class Axis>
-__device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x)[kMaxDim],
-                                              double t_n, Sel sel, Axis axis,
-                                              double (&val)[q_of(D)]) {
+// wall_mode gives mode j's factor at the wall point (cos and sin of its phase,
+// or its exponential in C), wall_term the mode's contribution to population k,
+// wall_close the terms outside the mode sum.
+
+// t: t_{n+1} full-way, t_n half-way
+template <int D, int V>
+__device__ __forceinline__ void wall_mode(const KParams& p, const double (&x)[kMaxDim], double t,
+                                          int j, double& C, double& S) {
+  const FieldDev& F = p.field;
+  double ph = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) ph += F.kvec[j][a] * (x[a] - p.u[a] * t);
+  if (wall_cos<V>(p)) {
+    sincos(ph + F.phase[j], &S, &C);
+  } else {
+    C = exp(ph);
+    S = 0.0;
+  }
+}
+
+template <int D, bool TAN, int V, int k, class Axis>
+__device__ __forceinline__ double wall_term(const KParams& p, int j, double C, double S,
+                                            Axis axis) {
   const FieldDev& F = p.field;
   const double dt = p.dt;
-  const bool full = wall_full<V>(p);
-  const bool is_cos = wall_cos<V>(p);
   const double o2 = p.P >= 2 ? 1.0 : 0.0;
   const double o3 = p.P >= 3 ? 1.0 : 0.0;
   const double o4 = p.P >= 4 ? 1.0 : 0.0;
   const double dt2 = dt * dt, dt3 = dt2 * dt;
-  const double t = full ? t_n + dt : t_n;
+  const bool is_cos = wall_cos<V>(p);
+  constexpr Vec4i c = vel_vec(D, k);
+  const double amp = F.amp[j];
+  const double w = -F.ku[j];
+  double pc = 0.0;
+  if constexpr (!TAN) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) pc += c.v[a] * F.kvec[j][a];
+  } else {
+    const int ja = axis(k);
+    double r = 0.0;  // c_kj / u_j
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      if (a == ja) r = c.v[a] * p.inv_u[a];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      if (a != ja) pc += (c.v[a] - r * p.u[a]) * F.kvec[j][a];
+    pc -= r * w;
+  }
+  if (wall_full<V>(p)) {
+    const double pv = pc + w;  // kappa . (c_k - u)
+    const double pv3 = pv * pv * pv;
+    if (is_cos) return amp * (C + (o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3) * S);
+    return amp * C * (1.0 - o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3);
+  }
+  constexpr int kb = opp_index(D, k);
+  const double wp = p.omega[k] + p.omega[kb];
+  const double wm = p.omega[k] - p.omega[kb];
+  const double T0 = wp;
+  const double T1 = o2 * wp * 0.5 * dt * w;
+  const double T2 = -o3 * (wp * dt2 / 8.0 * pc * pc + wm * dt2 / 4.0 * pc * w);
+  const double T3 = -o4 * (wp * (dt3 / 16.0 * pc * pc * w + dt3 / 24.0 * w * w * w) +
+                           wm * dt3 / 8.0 * pc * w * w);
+  if (is_cos) {
+    double Ck = C, Sk = S;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (c.v[a] == 0) continue;
+      const double cr = F.rot[j][a][0];
+      const double sr = c.v[a] * F.rot[j][a][1];
+      const double nc = Ck * cr + Sk * sr;
+      Sk = Sk * cr - Ck * sr;
+      Ck = nc;
+    }
+    return amp * ((T0 - T2) * Ck + (T3 - T1) * Sk);
+  }
+  double Ek = C;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (c.v[a] == 1) Ek *= F.rot[j][a][0];
+    if (c.v[a] == -1) Ek *= F.rot[j][a][1];
+  }
+  return amp * (T0 + T1 + T2 + T3) * Ek;
+}
+
+template <int D, int V, int k>
+__device__ __forceinline__ double wall_close(const KParams& p, double v, double t_n) {
+  if (wall_full<V>(p)) return p.omega[k] * (v + p.R * (t_n + p.dt));
+  constexpr int kb = opp_index(D, k);
+  const double o2 = p.P >= 2 ? 1.0 : 0.0;
+  const double wp = p.omega[k] + p.omega[kb];
+  return v + wp * p.R * t_n + o2 * wp * p.R * p.dt;
+}
+
+// Only the populations K0 <= k < K1 are evaluated; each val[k] is the same sum
+// over the modes in the same order whatever the range.  M0: the caller gives
+// mode 0's factor (C0, S0) from wall_mode.
+template <int D, bool TAN, int V, int K0 = 0, int K1 = q_of(D), bool M0 = false, class Sel,
+          class Axis>
+__device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x)[kMaxDim],
+                                              double t_n, Sel sel, Axis axis,
+                                              double (&val)[q_of(D)], double C0 = 0.0,
+                                              double S0 = 0.0) {
+  const double t = wall_full<V>(p) ? t_n + p.dt : t_n;
 #pragma unroll
   for (int k = K0; k < K1; ++k) val[k] = 0.0;
 #pragma unroll 1
-  for (int j = 0; j < F.nmodes; ++j) {
-    double ph = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) ph += F.kvec[j][a] * (x[a] - p.u[a] * t);
-    double C = 0.0, S = 0.0, E = 0.0;
-    if (is_cos)
-      sincos(ph + F.phase[j], &S, &C);
-    else
-      E = exp(ph);
-    const double amp = F.amp[j];
-    const double w = -F.ku[j];
+  for (int j = 0; j < p.field.nmodes; ++j) {
+    double C = C0, S = S0;
+    if (!M0 || j > 0) wall_mode<D, V>(p, x, t, j, C, S);
     static_for<K0, K1>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      constexpr Vec4i c = vel_vec(D, k);
       if (!sel(k)) return;
-      double pc = 0.0;
-      if constexpr (!TAN) {
-#pragma unroll
-        for (int a = 0; a < D; ++a) pc += c.v[a] * F.kvec[j][a];
-      } else {
-        const int ja = axis(k);
-        double r = 0.0;  // c_kj / u_j
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-          if (a == ja) r = c.v[a] * p.inv_u[a];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-          if (a != ja) pc += (c.v[a] - r * p.u[a]) * F.kvec[j][a];
-        pc -= r * w;
-      }
-      if (full) {
-        const double pv = pc + w;  // kappa . (c_k - u)
-        const double pv3 = pv * pv * pv;
-        if (is_cos)
-          val[k] += amp * (C + (o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3) * S);
-        else
-          val[k] += amp * E * (1.0 - o3 * 0.5 * dt * pv + o4 * dt3 / 24.0 * pv3);
-      } else {
-        constexpr int kb = opp_index(D, k);
-        const double wp = p.omega[k] + p.omega[kb];
-        const double wm = p.omega[k] - p.omega[kb];
-        const double T0 = wp;
-        const double T1 = o2 * wp * 0.5 * dt * w;
-        const double T2 = -o3 * (wp * dt2 / 8.0 * pc * pc + wm * dt2 / 4.0 * pc * w);
-        const double T3 = -o4 * (wp * (dt3 / 16.0 * pc * pc * w + dt3 / 24.0 * w * w * w) +
-                                 wm * dt3 / 8.0 * pc * w * w);
-        if (is_cos) {
-          double Ck = C, Sk = S;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            if (c.v[a] == 0) continue;
-            const double cr = F.rot[j][a][0];
-            const double sr = c.v[a] * F.rot[j][a][1];
-            const double nc = Ck * cr + Sk * sr;
-            Sk = Sk * cr - Ck * sr;
-            Ck = nc;
-          }
-          val[k] += amp * ((T0 - T2) * Ck + (T3 - T1) * Sk);
-        } else {
-          double Ek = E;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            if (c.v[a] == 1) Ek *= F.rot[j][a][0];
-            if (c.v[a] == -1) Ek *= F.rot[j][a][1];
-          }
-          val[k] += amp * (T0 + T1 + T2 + T3) * Ek;
-        }
-      }
+      val[k] += wall_term<D, TAN, V, k>(p, j, C, S, axis);
     });
   }
   static_for<K0, K1>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if (!sel(k)) return;
-    if (full) {
-      val[k] = p.omega[k] * (val[k] + p.R * t);
-    } else {
-      constexpr int kb = opp_index(D, k);
-      const double wp = p.omega[k] + p.omega[kb];
-      val[k] += wp * p.R * t_n + o2 * wp * p.R * dt;
-    }
+    val[k] = wall_close<D, V, k>(p, val[k], t_n);
   });
 }
+
+// Modes whose factors the half-way wall path of d = 3 keeps in registers
+constexpr int kWallModeCache = 4;
 
 // Slot of population k among those entering through the lower (c_k1 = +1) or
 // upper (c_k1 = -1) x_1 face; there are 2D - 1 of each.
@@ -388,10 +411,37 @@ __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, c
     ax[k] = TAN ? wall_axis<D, k>(r) : 0;
   });
   const bool half = !wall_full<V>(p);
-  // D4Q33 one population at a time, skipping those that enter from inside
-  // (each evaluated one recomputes the modes' sincos): its 33 sums and their
-  // coefficients held at once left the wall kernels at 256 VGPRs with spills
-  constexpr int G = D == 4 ? 1 : q_of(D);
+  // Half-way walls of d = 3 and all walls of d = 4 take one population at a
+  // time, skipping those that enter from inside: their sums and coefficients
+  // held at once took 256 VGPRs (d = 4 with spills), one wavefront per SIMD.
+  // Half-way walls of d = 3 with up to kWallModeCache modes first take every
+  // mode's factor once per node; otherwise the first mode's factor is taken
+  // once per node and the others' again for each population.
+  if constexpr (D == 3 && V >= 0 && (V & 1) == 0) {
+    if (p.field.nmodes <= kWallModeCache) {
+      double mc[kWallModeCache], ms[kWallModeCache];
+#pragma unroll
+      for (int j = 0; j < kWallModeCache; ++j)
+        if (j < p.field.nmodes) wall_mode<D, V>(p, x, t_n, j, mc[j], ms[j]);
+      static_for<0, q_of(D)>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if (!out[k]) return;
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < kWallModeCache; ++j)
+          if (j < p.field.nmodes)
+            v += wall_term<D, TAN, V, k>(p, j, mc[j], ms[j], [&](int kk) { return ax[kk]; });
+        v = wall_close<D, V, k>(p, v, t_n) - fstar_local(opp_index(D, k));
+        f[k] = static_cast<A>(v - p.omega[k] * ref);
+      });
+      return;
+    }
+  }
+  constexpr int G = (D == 4 || (D == 3 && V >= 0 && (V & 1) == 0)) ? 1 : q_of(D);
+  double c0 = 0.0, s0 = 0.0;
+  if constexpr (G < q_of(D)) {
+    if (p.field.nmodes > 0) wall_mode<D, V>(p, x, half ? t_n : t_n + p.dt, 0, c0, s0);
+  }
   static_for<0, (q_of(D) + G - 1) / G>([&](auto Gi) {
     constexpr int k0 = decltype(Gi)::value * G;
     constexpr int k1 = k0 + G < q_of(D) ? k0 + G : q_of(D);
@@ -401,8 +451,8 @@ __device__ __forceinline__ void wall_values(A (&f)[q_of(D)], const KParams& p, c
       if (!any) return;
     }
     double val[q_of(D)];
-    wall_analytic<D, TAN, V, k0, k1>(p, x, t_n, [&](int k) { return out[k]; },
-                                     [&](int k) { return ax[k]; }, val);
+    wall_analytic<D, TAN, V, k0, k1, (G < q_of(D))>(p, x, t_n, [&](int k) { return out[k]; },
+                                                    [&](int k) { return ax[k]; }, val, c0, s0);
     static_for<k0, k1>([&](auto K) {
       constexpr int k = decltype(K)::value;
       if (!out[k]) return;

@@ -230,6 +230,6 @@ def test_build_compiles_every_source_once():
     assert sorted(build.SOURCES) == on_disk
     cmd = build.compile_command(build.SOURCES[0], "x.o")
     assert "--offload-arch=gfx950" in cmd and "-packed-fp32-ops" in cmd and "-c" in cmd
-    # the d = 4 wall units keep their parameter block out of scratch
-    for src in ("walls_d4.hip", "walls_d4t.hip"):
+    # the d = 3 and d = 4 wall units keep their parameter block out of scratch
+    for src in ("walls_d3.hip", "walls_d3t.hip", "walls_d4.hip", "walls_d4t.hip"):
         assert "-instcombine-max-copied-from-constant-users=4000" in build.compile_command(src, "x.o")
