@@ -265,6 +265,24 @@ def test_exponential_field_d3(scheme):
                 precision="fp32_split")
 
 
+@pytest.mark.parametrize("scheme", ["fullway", "halfway"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_dirichlet_fields_past_the_mode_cache(scheme, precision):
+    """Six modes, more than the half-way wall kernels of d = 3 keep in registers:
+    they then take one population at a time, with every mode past the first
+    evaluated again per population (cosine and exponential fields, jets and
+    tangential wall data).  Four modes take the register path elsewhere."""
+    spec = inputs.random_cosines(3, [0.05, 0.1, 0.08], 1.0, seed=44, n_modes=6, kmax=1.0)
+    _check_pair(3, (27, 14, 12), 1.0 / 26, spec, 12, bc=[scheme] * 3, precision=precision)
+    _check_pair(3, (27, 14, 12), 1.0 / 26, spec, 12, bc=[scheme] * 3, precision=precision,
+                wall_data="tangential")
+    rng = np.random.default_rng(45)
+    espec = {"kind": "exp_sum", "amps": rng.normal(size=6).tolist(),
+             "kvecs": rng.uniform(-1.0, 1.0, size=(6, 3)).tolist(), "phases": [0.0] * 6,
+             "u": [0.06, -0.05, 0.08], "R": 0.5}
+    _check_pair(3, (27, 14, 12), 1.0 / 26, espec, 12, bc=[scheme] * 3, precision=precision)
+
+
 def test_example3_d4q33_halfway_small_u():
     spec = inputs.diagonal_sine(4, [1e-3] * 4)
     _check_pair(4, (10, 10, 10, 10), 0.2, spec, 8, bc=["halfway"] * 4, origin=[-1.0] * 4)
