@@ -283,6 +283,14 @@ def test_dirichlet_fields_past_the_mode_cache(scheme, precision):
     _check_pair(3, (27, 14, 12), 1.0 / 26, espec, 12, bc=[scheme] * 3, precision=precision)
 
 
+@pytest.mark.parametrize("scheme", ["fullway", "halfway"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_split", "fp32_hilo"])
+def test_dirichlet_d4_reduced_precision(scheme, precision):
+    """The D4Q33 wall-row kernels of the float32 storage modes against the oracle."""
+    spec = inputs.random_cosines(4, [0.05, 0.1, 0.08, 0.03], 1.0, seed=24, kmax=1.0)
+    _check_pair(4, (11, 8, 7, 6), 1.0 / 10, spec, 15, bc=[scheme] * 4, precision=precision)
+
+
 def test_example3_d4q33_halfway_small_u():
     spec = inputs.diagonal_sine(4, [1e-3] * 4)
     _check_pair(4, (10, 10, 10, 10), 0.2, spec, 8, bc=["halfway"] * 4, origin=[-1.0] * 4)
