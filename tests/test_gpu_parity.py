@@ -416,6 +416,19 @@ def test_degenerate_sizes(dims, bc):
     _check_pair(d, dims, 0.1, spec, 6, bc=bc)
 
 
+@pytest.mark.parametrize("dims,scheme", [((2, 3, 2), "fullway"), ((3, 3, 3), "halfway"),
+                                         ((70, 2, 3), "fullway"), ((65, 3, 2), "halfway"),
+                                         ((3, 2, 3, 2), "fullway"), ((2, 3, 2, 3), "halfway")])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_degenerate_sizes_with_walls(dims, scheme, precision):
+    """Lattices with two or three nodes on Dirichlet axes: every row, or every row
+    but one, lies on or next to a wall, so the two-step passes of d = 3 update
+    little or nothing themselves and the wall-row kernels carry the lattice."""
+    d = len(dims)
+    spec = inputs.random_cosines(d, [0.1, -0.05, 0.02, 0.04][:d], 0.3, seed=84, kmax=1.0)
+    _check_pair(d, dims, 0.1, spec, 6, bc=[scheme] * d, precision=precision)
+
+
 def test_zero_steps_and_error_reporting():
     from paper_2410_13165_amd import LbmError
     spec = inputs.random_cosines(2, [0.1, 0.1], 0.0, seed=82)
