@@ -80,6 +80,20 @@ def test_dirichlet_fp64(scheme, d, dims):
     _check_pair(d, dims, 1.0 / (dims[0] - 1), spec, 15, bc=[scheme] * d)
 
 
+@pytest.mark.parametrize("scheme", ["fullway", "halfway"])
+@pytest.mark.parametrize("d,dims,precision", [(2, (45, 33), "fp64"), (2, (45, 33), "fp32"),
+                                              (3, (35, 19, 23), "fp64"),
+                                              (3, (35, 19, 23), "fp32_split"),
+                                              (4, (11, 8, 7, 6), "fp64")])
+def test_dirichlet_tau_not_one_half(scheme, d, dims, precision):
+    """Walls with s = 1/tau != 2: the collision's (1 - s) f_k term, and with it the
+    half-way schemes' -f*_kbar of the node, no longer vanish."""
+    u = [0.05, 0.1, 0.08, 0.03][:d]
+    spec = inputs.random_cosines(d, u, 1.0, seed=25 + d, kmax=1.0)
+    _check_pair(d, dims, 1.0 / (dims[0] - 1), spec, 15, bc=[scheme] * d, tau=0.8,
+                precision=precision)
+
+
 @pytest.mark.parametrize("scheme,P", [("fullway", 1), ("fullway", 3), ("halfway", 1),
                                       ("halfway", 2), ("halfway", 3)])
 def test_dirichlet_lower_orders(scheme, P):
