@@ -102,6 +102,20 @@ def test_dirichlet_lower_orders(scheme, P):
     _check_pair(2, (n, n), 1.0 / 20, spec, 30, bc=[scheme] * 2, P=P)
 
 
+@pytest.mark.parametrize("scheme,P", [("fullway", 1), ("fullway", 3), ("halfway", 1),
+                                      ("halfway", 2), ("halfway", 3)])
+@pytest.mark.parametrize("d,dims,precision", [(3, (30, 17, 14), "fp64"),
+                                              (3, (30, 17, 14), "fp32_split"),
+                                              (4, (9, 8, 7, 6), "fp64")])
+def test_dirichlet_lower_orders_d3_d4(scheme, P, d, dims, precision):
+    """Wall orders below 4 (and K = 1 initialisation) in the wall-row kernels and
+    the two-step passes of d = 3 and the wall rows of d = 4."""
+    u = [0.05, 0.1, 0.08, 0.03][:d]
+    spec = inputs.random_cosines(d, u, 1.0, seed=30 + d + P, kmax=1.0)
+    _check_pair(d, dims, 1.0 / (dims[0] - 1), spec, 12, bc=[scheme] * d, P=P, K=1,
+                precision=precision)
+
+
 @pytest.mark.parametrize("scheme", ["fullway", "halfway"])
 def test_mixed_periodic_and_dirichlet_axes(scheme):
     spec = inputs.random_cosines(3, [0.05, -0.1, 0.08], 0.5, seed=31, kmax=1.0)
