@@ -294,7 +294,7 @@ def test_exponential_field_d3(scheme):
 
 
 @pytest.mark.parametrize("scheme", ["fullway", "halfway"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_split", "fp32_hilo"])
 def test_dirichlet_fields_past_the_mode_cache(scheme, precision):
     """Six modes, more than the half-way wall kernels of d = 3 keep in registers:
     they then take one population at a time, with every mode past the first
