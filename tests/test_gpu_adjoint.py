@@ -367,6 +367,11 @@ WALL_CASES = [
     (2, (8, 9), "halfway", "cos", 4, "tangential"),
     (3, (6, 5, 5), "fullway", "cos", 4, "jets"),
     (3, (5, 5, 4), "halfway", "cos", 4, "jets"),
+    (1, (11,), "fullway", "cos", 4, "jets"),
+    (1, (10,), "halfway", "exp", 4, "jets"),
+    (4, (4, 3, 3, 3), "fullway", "cos", 4, "jets"),
+    (4, (4, 3, 3, 3), "halfway", "cos", 3, "jets"),
+    (4, (3, 4, 3, 3), "fullway", "cos", 4, "tangential"),
 ]
 
 
@@ -387,7 +392,7 @@ def test_wall_data_gradient_equals_oracle(case, tau):
     differences of the oracle run with the perturbed wall field: exact in a_j
     (L is quadratic in the amplitudes), O(h^2) in theta_j."""
     d, dims, scheme, kind, P, wall_data = WALL_CASES[case]
-    u = [0.12, -0.07, 0.05][:d]
+    u = [0.12, -0.07, 0.05, 0.04][:d]
     spec = _wall_spec(d, kind, u, 110 + case)
     dx, steps, every = 0.1, 7, 3
     rng = np.random.default_rng(120 + case)
