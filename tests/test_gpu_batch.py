@@ -52,6 +52,33 @@ def test_batch_matches_oracle_per_instance(precision, tol, K):
             assert rel_l2(got, run.phi()) <= tol, (i, sp)
 
 
+@pytest.mark.parametrize("d", [1, 3, 4])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_batch_other_dimensions_match_oracle(d, precision, tol):
+    """Batches of D1Q3, D3Q19 and D4Q33 lattices of uneven sizes, each with its own
+    tau and u (the single-step batch kernel), against per-instance oracle runs."""
+    from paper_2410_13165_amd import Batch
+    rng = np.random.default_rng(60 + d)
+    lo, hi = {1: (20, 70), 3: (5, 12), 4: (3, 7)}[d]
+    specs = []
+    for _ in range(5):
+        dims = tuple(int(rng.integers(lo, hi)) for _ in range(d))
+        specs.append({"dims": dims, "tau": float(rng.uniform(0.5, 1.2)),
+                      "u": rng.uniform(-0.3, 0.3, size=d).tolist(), "dx": 1.0 / dims[0],
+                      "K": 3})
+    parts, phi0 = _concat_phi0(specs, 700 + d)
+    steps = 12
+    with Batch(d, specs, precision=precision) as b:
+        b.set_initial(phi0)
+        b.step(steps)
+        for i, sp in enumerate(specs):
+            prob = oracle_problem(d, sp["dims"], sp["dx"], None, u=sp["u"], tau=sp["tau"], K=3)
+            run = O.Run(prob, phi0=to_oracle_order(parts[i].reshape(tuple(reversed(sp["dims"])))))
+            run.step(steps)
+            got = to_oracle_order(b.instance(i).phi().cpu().numpy())
+            assert rel_l2(got, run.phi()) <= tol, (i, sp)
+
+
 def test_tuner_restores_state_and_configs_agree():
     """Every block shape gives bitwise identical states; tuning leaves the
     state where it was."""
