@@ -343,6 +343,27 @@ def test_set_initial_noise_and_fd_gradient(K):
         lat.close()
 
 
+@pytest.mark.parametrize("d,dims", [(1, (50,)), (3, (20, 14, 9)), (4, (9, 7, 6, 5))])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_split", 2e-5)])
+@pytest.mark.parametrize("K", [1, 3])
+def test_set_initial_fd_gradient_all_dims(d, dims, precision, tol, K):
+    """A device phi^0 with the fourth-order finite-difference gradient on every
+    axis of d = 1, 3 and 4 (and K = 1), in float64 and the split storage."""
+    u = [0.3, -0.2, 0.1, 0.15][:d]
+    phi0 = inputs.noise(tuple(reversed(dims)), seed=5 + d)  # GPU layout (N_d, ..., N_1)
+    prob = oracle_problem(d, dims, 1.0 / dims[0], None, u=u, K=K)
+    run = O.Run(prob, phi0=to_oracle_order(phi0))
+    lat = gpu_lattice(d, dims, 1.0 / dims[0], None, u=u, K=K, precision=precision)
+    try:
+        lat.set_initial(torch.from_numpy(phi0.ravel()))
+        for n in (0, 1, 14):
+            lat.step(n - lat.info()["step"])
+            run.step(n - run.n)
+            assert rel_l2(_phi(lat), run.phi()) <= tol, n
+    finally:
+        lat.close()
+
+
 def test_set_initial_with_gradient():
     d, dims = 3, (20, 12, 9)
     rng = np.random.default_rng(9)
