@@ -380,6 +380,18 @@ __device__ __forceinline__ void wall_analytic(const KParams& p, const double (&x
 // Modes whose factors the half-way wall path of d = 3 keeps in registers
 constexpr int kWallModeCache = 4;
 
+// The population in slot s (0 <= s < 2D - 1) of those entering through the
+// lower (cx = +1) or upper (cx = -1) x_1 face: xface_slot's inverse.
+constexpr int face_pop(int D, int cx, int s) {
+  int n = 0;
+  for (int k = 0; k < q_of(D); ++k) {
+    if (vel_comp(D, k, 0) != cx) continue;
+    if (n == s) return k;
+    ++n;
+  }
+  return -1;
+}
+
 // Slot of population k among those entering through the lower (c_k1 = +1) or
 // upper (c_k1 = -1) x_1 face; there are 2D - 1 of each.
 constexpr int xface_slot(int D, int k) {
@@ -690,12 +702,22 @@ __global__ void __launch_bounds__((FuseFwdShape<T, HALF>::NT))
           f[k] = A[k * ps + idx];
         });
         if (HALF && (ri.lo[0] || ri.hi[0])) {
-          static_for<0, Q>([&](auto K) {
-            constexpr int k = decltype(K)::value;
-            constexpr int cx = vel_comp(D, k, 0);
-            if constexpr (cx != 0) {
-              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] -= A[opp_index(D, k) * ps + node];
-            }
+          // the node's own f*_kbar of the face's 2D - 1 unknowns, every load
+          // issued before any is used (one branch per population had the
+          // compiler wait for each load in turn)
+          const bool lo = ri.lo[0];
+          T sb[2 * D - 1];
+          static_for<0, 2 * D - 1>([&](auto Sx) {
+            constexpr int sl = decltype(Sx)::value;
+            constexpr int kl = face_pop(D, 1, sl), kh = face_pop(D, -1, sl);
+            sb[sl] = A[(lo ? opp_index(D, kl) : opp_index(D, kh)) * ps + node];
+          });
+          asm volatile("" ::: "memory");
+          static_for<0, 2 * D - 1>([&](auto Sx) {
+            constexpr int sl = decltype(Sx)::value;
+            constexpr int kl = face_pop(D, 1, sl), kh = face_pop(D, -1, sl);
+            if (lo) f[kl] -= sb[sl];
+            else f[kh] -= sb[sl];
           });
         }
         collide_vals<D, T>(f, p);
@@ -754,28 +776,36 @@ __global__ void __launch_bounds__((FuseFwdShape<T, HALF>::NT))
           f[k] = lds[fuse_slot<false, k>(it - src_it) * R + rr];
         });
         if (ri.lo[0] || ri.hi[0]) {
-          static_for<0, Q>([&](auto K) {
-            constexpr int k = decltype(K)::value;
-            constexpr int cx = vel_comp(D, k, 0);
-            if constexpr (cx != 0) {
-              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) f[k] = B[k * ps + p.xoff + row];
-            }
-          });
-        }
-        if (HALF && (ri.lo[0] || ri.hi[0])) {
+          // the face's 2D - 1 unknowns from B's row slots (half-way: minus the
+          // node's own step-1 f*_kbar, from LDS), every load issued before
+          // any is used
+          const bool lo = ri.lo[0];
           const int own = (oy + 1) * RX + (ox + 1);
-          static_for<0, Q>([&](auto K) {
+          // LDS element of the own f*_kbar of face population k on face fc
+          auto own_at = [&](auto K, int fc) {
             constexpr int k = decltype(K)::value;
-            constexpr int cx = vel_comp(D, k, 0);
-            if constexpr (cx != 0) {
-              constexpr int kb = opp_index(D, k);
-              if ((cx == 1) ? ri.lo[0] : ri.hi[0]) {
-                if constexpr (vel_comp(D, k, 2) == 1)
-                  f[k] -= side[(((it - 1) & 1) * 2 + (cx == 1 ? 0 : 1)) * RY + oy + 1];
-                else
-                  f[k] -= lds[fuse_slot<false, kb>(it - 1) * R + own];
-              }
-            }
+            if constexpr (vel_comp(D, k, 2) == 1)
+              return S::SLOTS * R + (((it - 1) & 1) * 2 + fc) * RY + oy + 1;
+            else
+              return fuse_slot<false, opp_index(D, k)>(it - 1) * R + own;
+          };
+          T fx[2 * D - 1], sb[2 * D - 1];
+          static_for<0, 2 * D - 1>([&](auto Sx) {
+            constexpr int sl = decltype(Sx)::value;
+            constexpr int kl = face_pop(D, 1, sl), kh = face_pop(D, -1, sl);
+            fx[sl] = B[(lo ? kl : kh) * ps + p.xoff + row];
+            if constexpr (HALF)
+              sb[sl] = lds[lo ? own_at(std::integral_constant<int, kl>{}, 0)
+                              : own_at(std::integral_constant<int, kh>{}, 1)];
+          });
+          asm volatile("" ::: "memory");
+          static_for<0, 2 * D - 1>([&](auto Sx) {
+            constexpr int sl = decltype(Sx)::value;
+            constexpr int kl = face_pop(D, 1, sl), kh = face_pop(D, -1, sl);
+            T v = fx[sl];
+            if constexpr (HALF) v -= sb[sl];
+            if (lo) f[kl] = v;
+            else f[kh] = v;
           });
         }
         collide_store<D, T>(f, B, ps, node, p);
