@@ -392,25 +392,34 @@ def run_sweep(steps=None, count=None, precision="fp32"):
         print(f"# sweep: tuned {cfg}", file=sys.stderr, flush=True)
         m0 = b.moments()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        # sum phi^2 after every chunk gives the late-time growth rates; those
+        # readouts sit between timed chunks, outside the timed work
+        marks = [(0, m0[:, 1])]
+        elapsed = 0.0
+        done = 0
         chunk = 500
-        for done in range(0, steps, chunk):
-            b.step(min(chunk, steps - done))
+        while done < steps:
+            todo = min(chunk, steps - done)
+            t0 = time.perf_counter()
+            b.step(todo)
             torch.cuda.synchronize()
-            print(f"# sweep: {min(done + chunk, steps)} steps", file=sys.stderr, flush=True)
-        t1 = time.perf_counter()
+            elapsed += time.perf_counter() - t0
+            done += todo
+            marks.append((done, b.moments()[:, 1]))
+            print(f"# sweep: {done} steps", file=sys.stderr, flush=True)
         m1 = b.moments()
         min_om = np.array([b.instance(i).info()["min_omega"] for i in range(len(specs))])
     taus = np.array([sp["tau"] for sp in specs])
     growth = np.sqrt(m1[:, 1] / m0[:, 1])
     finite = np.isfinite(growth)
-    pred = sweep_prediction(specs, growth, m0[:, 3], m1[:, 3], min_om, steps)
+    pred = sweep_prediction(specs, growth, m0[:, 3], m1[:, 3], min_om, steps,
+                            late_rate=late_growth_rates(marks))
     return {
         "workload": (f"{len(specs)} periodic D2Q9 lattices (sizes 64^2..512^2), {precision}, "
                      f"{steps} steps, tau~U(0.5,2), sigma~U(-0.75,0.75)^2, noise init"),
         "nodes": nodes,
-        "seconds": t1 - t0,
-        "mlups": nodes * steps / (t1 - t0) / 1e6,
+        "seconds": elapsed,
+        "mlups": nodes * steps / elapsed / 1e6,
         "config": cfg,
         "grew_1e3": int(np.sum(~finite | (growth > 1e3))),
         "bounded": int(np.sum(finite & (growth <= 1.0 + 1e-6))),
@@ -419,13 +428,41 @@ def run_sweep(steps=None, count=None, precision="fp32"):
     }
 
 
-def sweep_prediction(specs, growth, ent0, ent1, min_om, steps):
+def late_growth_rates(marks):
+    """Per instance, log of the growth of ||phi|| per step over the second half
+    of its readable run: marks is a list of (step, sum phi^2 per instance); an
+    instance whose norm overflowed is read up to its last finite readout S_e,
+    from the readout nearest S_e / 2 (NaN where fewer than two readouts apart)."""
+    import numpy as np
+    steps = np.array([m[0] for m in marks])
+    ss = np.stack([m[1] for m in marks])  # (readouts, instances)
+    ok = np.isfinite(ss) & (ss > 0)
+    rate = np.full(ss.shape[1], np.nan)
+    for i in range(ss.shape[1]):
+        good = np.nonzero(ok[:, i])[0]
+        if good.size < 2:
+            continue
+        e = good[-1]
+        b = good[np.argmin(np.abs(steps[good] - steps[e] / 2))]
+        if b >= e:
+            b = good[-2]
+        rate[i] = 0.5 * np.log(ss[e, i] / ss[b, i]) / (steps[e] - steps[b])
+    return rate
+
+
+def sweep_prediction(specs, growth, ent0, ent1, min_om, steps, late_rate=None):
     """Per instance, the growth of ||phi|| and of the total entropy over the run
     against what the parameters predict: the largest spectral radius of the
     amplification matrix over the instance's wave numbers (a grid of
     min(n, 256)^2 of them, a subset of the instance's own when n > 256),
     computed on the GPU by lbm_stability_map, and the entropy criterion
-    min omega > 0 (Prop. 1)."""
+    min omega > 0 (Prop. 1).
+
+    The rate log(growth)/steps over the whole run carries log c / steps, where
+    c is the share of the noise initial data in the fastest-growing modes (about
+    1/n for n^2 modes).  late_rate (late_growth_rates) starts where those modes
+    already dominate and also covers instances whose norm overflowed before the
+    end, so it is compared with log rho as well (growth_rate_late_*)."""
     import numpy as np
     import torch
     from paper_2410_13165_amd import lbm
@@ -447,6 +484,17 @@ def sweep_prediction(specs, growth, ent0, ent1, min_om, steps):
     # growing instances: the measured rate log(growth)/steps tends to log rho
     sel = unstable & grew & finite
     rel_rate = np.abs(rate[sel] - logrho[sel]) / logrho[sel] if np.any(sel) else np.zeros(0)
+    late = {}
+    if late_rate is not None:
+        sel_l = unstable & grew & np.isfinite(late_rate)
+        rel_l = (np.abs(late_rate[sel_l] - logrho[sel_l]) / logrho[sel_l]
+                 if np.any(sel_l) else np.zeros(0))
+        late = {
+            "growth_rate_instances": int(sel.sum()),
+            "growth_rate_late_instances": int(sel_l.sum()),
+            "growth_rate_late_rel_err_median": float(np.median(rel_l)) if rel_l.size else None,
+            "growth_rate_late_rel_err_max": float(np.max(rel_l)) if rel_l.size else None,
+        }
     ent_ratio = ent1 / ent0
     pos = min_om > 0
     return {
@@ -460,6 +508,7 @@ def sweep_prediction(specs, growth, ent0, ent1, min_om, steps):
         "min_omega_positive": int(pos.sum()),
         "entropy_grew_where_min_omega_positive": int(np.sum(pos & ~(ent_ratio <= 1.0 + 1e-9))),
         "rho_max": float(np.max(rho)),
+        **late,
     }
 
 
