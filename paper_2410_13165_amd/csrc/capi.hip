@@ -1271,6 +1271,21 @@ std::string tune_key(const lbm_batch* b) {
   return k;
 }
 
+// the single-step block shapes (tx, ty) the tuner times
+constexpr int kTuneShapes[3][2] = {{64, 4}, {128, 2}, {256, 1}};
+
+// An entry is used only if it names a launch the tuner itself could have
+// chosen: a file written by another build, edited or cut short could
+// otherwise set a zero row step or a block the kernels were not built for.
+bool tune_entry_valid(const TuneEntry& e) {
+  const bool form = e.form == LBM_BATCH_PER_PAIR || e.form == LBM_BATCH_RESIDENT;
+  const bool rows = e.ychunk == 0 || (e.ychunk >= 8 && e.ychunk <= 64);
+  bool shape = false;
+  for (const auto& sh : kTuneShapes) shape = shape || (e.tx == sh[0] && e.ty == sh[1]);
+  return form && rows && shape && std::isfinite(e.ms) && e.ms >= 0.0;
+}
+
+// Lines that do not parse, or whose entry is not valid, are skipped.
 void tune_file_load() {
   if (g_tune_file_read) return;
   g_tune_file_read = true;
@@ -1278,11 +1293,15 @@ void tune_file_load() {
   if (!path || !*path) return;
   std::FILE* f = std::fopen(path, "r");
   if (!f) return;
-  unsigned long long hash = 0;
-  TuneEntry e;
-  while (std::fscanf(f, "%llx %d %d %d %d %lf", &hash, &e.form, &e.ychunk, &e.tx, &e.ty, &e.ms) ==
-         6)
-    g_tune_file[hash] = e;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    unsigned long long hash = 0;
+    TuneEntry e;
+    if (std::sscanf(line, "%llx %d %d %d %d %lf", &hash, &e.form, &e.ychunk, &e.tx, &e.ty,
+                    &e.ms) == 6 &&
+        tune_entry_valid(e))
+      g_tune_file[hash] = e;
+  }
   std::fclose(f);
 }
 
@@ -1507,8 +1526,7 @@ int lbm_batch_tune(lbm_batch* b, int trial_steps, int32_t* config_out, double* m
     };
     // single-step block shapes (remainder steps, batches without pairs)
     double best_single = 1e300;
-    const int shapes[3][2] = {{64, 4}, {128, 2}, {256, 1}};
-    for (const auto& sh : shapes) {
+    for (const auto& sh : kTuneShapes) {
       rc = batch_tiles(b, sh[0], sh[1]);
       double ms = 0.0;
       if (rc == LBM_OK) rc = trial(trial_steps, false, &ms);

@@ -371,3 +371,56 @@ def test_tuner_times_launch_forms_restores_state_and_caches(tmp_path, monkeypatc
         assert again["cached"] and again["form"] == cfg["form"] and again["ychunk"] == cfg["ychunk"]
     fields = cache.read_text().split()
     assert len(fields) == 6 and int(fields[2]) == cfg["ychunk"]
+
+
+_TUNE_CHILD = r"""
+import json, sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_2410_13165_amd import Batch, inputs
+specs = [{"dims": (83, 45), "tau": 0.8, "u": [0.1, -0.2], "dx": 1.0 / 83},
+         {"dims": (40, 61), "tau": 1.1, "u": [-0.3, 0.05], "dx": 1.0 / 40}]
+phi0 = torch.from_numpy(np.concatenate(
+    [inputs.noise(tuple(reversed(sp["dims"])), 900 + i, std=1e-3).ravel()
+     for i, sp in enumerate(specs)]))
+with Batch(2, specs, precision="fp32") as b:
+    b.set_initial(phi0)
+    cfg = b.tune(2)
+    b.step(5)
+    print(json.dumps(cfg), flush=True)
+"""
+
+
+def test_tuner_ignores_invalid_cache_entries(tmp_path):
+    """An entry of the LBM_TUNE_CACHE file that names no launch the tuner could
+    have chosen (zero rows per tile, an unknown launch form, a block shape the
+    kernels were not built for) is not used: the batch is tuned again.  Each
+    run is a child process, since the file is read once per process."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, LBM_TUNE_CACHE=str(cache))
+
+    def child():
+        print("[tune-cache] child run", flush=True)
+        r = subprocess.run([sys.executable, "-c", _TUNE_CHILD, root], env=env,
+                           capture_output=True, text=True, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    first = child()
+    assert not first["cached"]
+    line = cache.read_text().split("\n")[0].split()
+    assert len(line) == 6
+    # same key hash, values no launch accepts
+    cache.write_text(f"{line[0]} 7 0 64 0 0.5\nnot a line\n")
+    second = child()
+    assert not second["cached"]
+    assert second["form"] in ("per_pair", "resident") and 8 <= second["ychunk"] <= 64
+    # the re-tuned entry is appended and served to the next process
+    third = child()
+    assert third["cached"] and third["ychunk"] == second["ychunk"]
